@@ -1,0 +1,473 @@
+"""Oracle for the multibeam transient hot path (test infrastructure only).
+
+Plain, slow and obviously correct FP64 CPU implementation of what the GPU
+path computes: the cold-plasma delay table (Eq. 1), the thresholding RFI
+pass (Sec. 2.2.1), brute-force dedispersion (Sec. 2.2.2), per-DM detrending
+and normalisation (Sec. 2.2.3) and the n-sigma event threshold (Sec. 2.3).
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It shares no code with the GPU path; the two meet only
+through the seeded input generators, which hold none of the method's
+arithmetic.
+
+Readings of passages where the paper is silent or ambiguous are marked
+"Reading:" in the docstrings; each one is also listed with its alternatives
+in the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+
+# Eq. (1): delay ~= 4.15e6 ms * (f1^-2 - f2^-2) * DM, f in MHz.
+# Reading: the printed constant is used exactly, expressed in seconds.
+DISPERSION_CONSTANT_S_MHZ2 = 4150.0
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+
+def _clib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, i32p, dp, fp = (ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float))
+        lib.oracle_dedisperse_f64.argtypes = [dp, i64, i64, i32p, i64, i64, dp, i64, ctypes.c_int]
+        lib.oracle_dedisperse_f32.argtypes = [fp, i64, i64, i32p, i64, i64, dp, i64, ctypes.c_int]
+        lib.oracle_dedisperse_rows_f64.argtypes = [dp, i64, i64, i32p, i64, i32p, i64, dp, i64, ctypes.c_int]
+        lib.oracle_dedisperse_rows_f32.argtypes = [fp, i64, i64, i32p, i64, i32p, i64, dp, i64, ctypes.c_int]
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_clib().oracle_max_threads())
+
+
+# --------------------------------------------------------------------------
+# Observing and survey parameters (Sec. 1.1 band, Sec. 2.2.2 DM trials)
+# --------------------------------------------------------------------------
+
+def channel_freqs(nchans: int, f_ch0_mhz: float, df_mhz: float) -> np.ndarray:
+    """Centre frequency of every channel, f_c = f_ch0 + c*df (FP64).
+
+    Reading: a channel's frequency is its centre; df may be negative for a
+    band stored in descending frequency order.
+    """
+    return f_ch0_mhz + np.arange(nchans, dtype=np.float64) * df_mhz
+
+
+def dm_trials(ndms: int, dm_start: float, dm_step: float) -> np.ndarray:
+    """Trial DMs, DM_d = dm_start + d*dm_step (a product, never a running sum)."""
+    return dm_start + np.arange(ndms, dtype=np.float64) * dm_step
+
+
+def delay_table(nchans: int, f_ch0_mhz: float, df_mhz: float, tsamp_s: float,
+                ndms: int, dm_start: float, dm_step: float) -> np.ndarray:
+    """Integer sample delay of every (DM, channel) pair, Eq. (1).
+
+    s[d][c] = floor(k * DM_d * (1/f_c^2 - 1/f_ref^2) / tsamp + 1/2), k = 4150 s MHz^2.
+
+    Reading: f_ref is the highest channel centre (so its delay is 0 for
+    every DM and DM 0 reduces to the plain channel sum); rounding is to the
+    nearest sample, halves away from zero.  Evaluated in FP64.
+    """
+    f = channel_freqs(nchans, f_ch0_mhz, df_mhz)
+    f_ref = f.max()
+    dms = dm_trials(ndms, dm_start, dm_step)
+    inv = 1.0 / (f * f) - 1.0 / (f_ref * f_ref)
+    k = (DISPERSION_CONSTANT_S_MHZ2 * dms)[:, None] * inv[None, :] / tsamp_s
+    return np.floor(k + 0.5).astype(np.int32)
+
+
+def max_delay(delays: np.ndarray) -> int:
+    return int(delays.max()) if delays.size else 0
+
+
+# --------------------------------------------------------------------------
+# RFI thresholding, Sec. 2.2.1 (bandpass correction, channel thresholding,
+# spectrum thresholding, in that order)
+# --------------------------------------------------------------------------
+
+@dataclass
+class RfiParams:
+    """Tuning factors of the thresholding pass (Sec. 2.2.1).
+
+    poly_order: p of the bandpass polynomial (paper leaves p open; reading: 3).
+    window:     W_c, the channel-chunk width in samples (reading: 256).
+    k_mask, k_chan, k_spec: threshold factors in units of the relevant noise
+                std (reading: 5 each, matching a "5 sigma" RFI threshold).
+    mask_passes: how many fit-and-mask rounds pick the channels to interpolate
+                before the final fit (reading: 1; more rounds catch bright
+                channels hidden by brighter ones in the first RMSE).
+    """
+    poly_order: int = 3
+    window: int = 256
+    k_mask: float = 5.0
+    k_chan: float = 5.0
+    k_spec: float = 5.0
+    mask_passes: int = 1
+
+
+@dataclass
+class RfiResult:
+    y: np.ndarray                 # cleaned samples, FP64 [C][T]
+    bandpass: np.ndarray          # B[c], time-averaged power
+    masked: np.ndarray            # bool[C], channels replaced by neighbour mean
+    bandpass_interp: np.ndarray   # B~[c] after masking
+    fit: np.ndarray               # f[c], fitted bandpass
+    rmse0: float                  # RMSE of the first fit (mask criterion)
+    rmse: float                   # RMSE of the final fit
+    sigma: float                  # per-sample noise std implied by rmse
+    chunk_means: np.ndarray       # m[c][j] of bandpass-corrected data
+    chunk_len: np.ndarray         # L_j
+    chunk_flags: np.ndarray       # F[c][j] before neighbour extension
+    chunk_flags_ext: np.ndarray   # F'[c][j] after neighbour extension
+    spectrum_means: np.ndarray    # s[t] after channel thresholding
+    spectrum_flags: np.ndarray    # G[t]
+    near_ties: dict = field(default_factory=dict)
+
+
+def _lstsq_qr(V: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Least squares by Householder QR (LAPACK geqrf via numpy)."""
+    q, r = np.linalg.qr(V)
+    return scipy.linalg.solve_triangular(r, q.T @ b, lower=False)
+
+
+def poly_basis(nchans: int, p: int) -> np.ndarray:
+    """Vandermonde matrix of degree p on u_c = (2c-(C-1))/(C-1) in [-1, 1]."""
+    u = (2.0 * np.arange(nchans, dtype=np.float64) - (nchans - 1)) / (nchans - 1)
+    return np.vander(u, p + 1, increasing=True)
+
+
+def fit_bandpass(B: np.ndarray, p: int):
+    """p-th order least-squares polynomial fit; returns (fit, rmse)."""
+    V = poly_basis(B.shape[0], p)
+    coef = _lstsq_qr(V, B)
+    fit = V @ coef
+    r = B - fit
+    return fit, float(np.sqrt(np.mean(r * r)))
+
+
+def interpolate_masked(B: np.ndarray, masked: np.ndarray) -> np.ndarray:
+    """Replace each masked channel by the mean of its nearest unmasked
+    neighbour on each side (one side only at a band edge)."""
+    keep = np.flatnonzero(~masked)
+    if keep.size == 0:
+        raise ValueError("every channel was masked; the bandpass cannot be fitted")
+    out = B.copy()
+    for c in np.flatnonzero(masked):
+        i = int(np.searchsorted(keep, c))
+        vals = []
+        if i > 0:
+            vals.append(B[keep[i - 1]])
+        if i < keep.size:
+            vals.append(B[keep[i]])
+        out[c] = (vals[0] + vals[1]) * 0.5 if len(vals) == 2 else vals[0]
+    return out
+
+
+def chunk_bounds(T: int, W: int):
+    """Non-overlapping windows of width W along time; the last may be short."""
+    J = (T + W - 1) // W
+    starts = np.arange(J, dtype=np.int64) * W
+    lens = np.minimum(W, T - starts)
+    return starts, lens
+
+
+def rfi_clean(x: np.ndarray, params: RfiParams = RfiParams()) -> RfiResult:
+    """The three-stage thresholding pass of Sec. 2.2.1 on one chunk x[C][T].
+
+    1. Bandpass correction: B[c] = time average of channel c.  Fit a degree-p
+       polynomial; channels whose residual exceeds k_mask*RMSE0 are masked and
+       replaced by the mean of their nearest unmasked neighbours; refit -> f[c]
+       and RMSE.  With mask_passes > 1 the fit-and-mask round repeats on the
+       interpolated bandpass, the mask only growing, before the final fit.  Reading: the RMSE is turned into a per-sample noise estimate
+       sigma = RMSE*sqrt(T*C/(C-p-1)) (B[c] is a mean of T samples and the fit
+       has p+1 parameters), and f is subtracted from every spectrum.
+    2. Channel thresholding: partition each channel into chunks of W_c; a chunk
+       whose mean |m| exceeds k_chan*sigma/sqrt(L_j) is flagged together with
+       its time-adjacent chunks j-1, j+1 of the same channel.  Flagged samples
+       take the fitted bandpass value, i.e. 0 after correction.
+    3. Spectrum thresholding: the mean over all channels of each (channel-
+       cleaned) spectrum is compared with k_spec*sigma/sqrt(C); a flagged
+       spectrum is replaced by the fitted bandpass (0 after correction).
+    Reading: every comparison is two-sided and strict (|.| > threshold), so
+    zeroed packet gaps (Sec. 2.1), a negative excursion, are caught too.
+    """
+    p, W = int(params.poly_order), int(params.window)
+    x64 = np.asarray(x).astype(np.float64)
+    C, T = x64.shape
+    if C < p + 2:
+        raise ValueError("need more channels than polynomial parameters")
+    if T < 1 or W < 1:
+        raise ValueError("empty chunk or window")
+
+    # 1. Bandpass correction
+    B = x64.sum(axis=1) / T
+    masked = np.zeros(C, dtype=bool)
+    Bi = B
+    r0, rmse0 = None, None
+    for _ in range(max(int(params.mask_passes), 1)):
+        fit_i, rmse_i = fit_bandpass(Bi, p)
+        r_i = B - fit_i
+        if r0 is None:
+            r0, rmse0 = r_i, rmse_i
+        masked = masked | (np.abs(r_i) > params.k_mask * rmse_i)
+        Bi = interpolate_masked(B, masked)
+    f, rmse = fit_bandpass(Bi, p)
+    sigma = rmse * math.sqrt(T * C / (C - p - 1))
+    y = x64 - f[:, None]
+
+    # 2. Channel thresholding
+    starts, lens = chunk_bounds(T, W)
+    m = np.add.reduceat(y, starts, axis=1) / lens[None, :]
+    thr_chan = params.k_chan * sigma / np.sqrt(lens.astype(np.float64))
+    F = np.abs(m) > thr_chan[None, :]
+    Fx = F.copy()
+    Fx[:, 1:] |= F[:, :-1]
+    Fx[:, :-1] |= F[:, 1:]
+    sample_flags = np.repeat(Fx, W, axis=1)[:, :T]
+    y[sample_flags] = 0.0
+
+    # 3. Spectrum thresholding (on the channel-cleaned data)
+    s = y.sum(axis=0) / C
+    thr_spec = params.k_spec * sigma / math.sqrt(C)
+    G = np.abs(s) > thr_spec
+    y[:, G] = 0.0
+
+    # Distance of every statistic from its threshold, in units of the noise
+    # std of that statistic: a value within 1e-9 of a threshold is a near tie
+    # whose flag depends on rounding.
+    ties = {}
+    eps = 1e-9
+    if rmse0 > 0:
+        dm_ = np.abs(np.abs(r0) - params.k_mask * rmse0) / rmse0
+        ties["mask_min"] = float(dm_.min())
+        ties["mask_count"] = int((dm_ < eps).sum())
+    if sigma > 0:
+        unit_c = sigma / np.sqrt(lens.astype(np.float64))
+        dc = np.abs(np.abs(m) - thr_chan[None, :]) / unit_c[None, :]
+        ties["chunk_min"] = float(dc.min())
+        ties["chunk_count"] = int((dc < eps).sum())
+        ds_ = np.abs(np.abs(s) - thr_spec) / (sigma / math.sqrt(C))
+        ties["spectrum_min"] = float(ds_.min())
+        ties["spectrum_count"] = int((ds_ < eps).sum())
+
+    return RfiResult(y=y, bandpass=B, masked=masked, bandpass_interp=Bi, fit=f,
+                     rmse0=rmse0, rmse=rmse, sigma=sigma, chunk_means=m,
+                     chunk_len=lens, chunk_flags=F, chunk_flags_ext=Fx,
+                     spectrum_means=s, spectrum_flags=G, near_ties=ties)
+
+
+# --------------------------------------------------------------------------
+# Brute-force dedispersion, Sec. 2.2.2
+# --------------------------------------------------------------------------
+
+def _as_c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def dedisperse(y: np.ndarray, delays: np.ndarray, nout: int | None = None,
+               nthreads: int | None = None) -> np.ndarray:
+    """D[d][t] = sum_c y[c][t + s[d][c]] for t in [0, nout), FP64.
+
+    y is FP64 (cleaned) or any stored type (widened exactly through f32).
+    Reading: only outputs whose every term lies inside the input are formed,
+    nout = T - s_max by default (no zero padding at the edge).
+    """
+    C, T = y.shape
+    ndms = delays.shape[0]
+    assert delays.shape[1] == C
+    smax = max_delay(delays)
+    if nout is None:
+        nout = T - smax
+    if nout < 0 or nout + smax > T:
+        raise ValueError("input too short for the requested outputs")
+    out = np.empty((ndms, max(nout, 0)), dtype=np.float64)
+    if nout == 0 or ndms == 0:
+        return out
+    nt = nthreads or max_threads()
+    dl = _as_c(delays, np.int32)
+    lib = _clib()
+    P = ctypes.POINTER
+    if y.dtype == np.float64:
+        ya = _as_c(y, np.float64)
+        lib.oracle_dedisperse_f64(ya.ctypes.data_as(P(ctypes.c_double)), C, T,
+                                  dl.ctypes.data_as(P(ctypes.c_int32)), ndms, nout,
+                                  out.ctypes.data_as(P(ctypes.c_double)), nout, nt)
+    else:
+        ya = _as_c(y, np.float32)
+        lib.oracle_dedisperse_f32(ya.ctypes.data_as(P(ctypes.c_float)), C, T,
+                                  dl.ctypes.data_as(P(ctypes.c_int32)), ndms, nout,
+                                  out.ctypes.data_as(P(ctypes.c_double)), nout, nt)
+    return out
+
+
+def dedisperse_rows(y: np.ndarray, delays: np.ndarray, rows, nout: int,
+                    nthreads: int | None = None) -> np.ndarray:
+    """The same sum for selected DM rows only (full-size sampled checks)."""
+    C, T = y.shape
+    rows = _as_c(np.asarray(rows), np.int32)
+    assert nout + max_delay(delays[rows]) <= T
+    out = np.empty((rows.shape[0], nout), dtype=np.float64)
+    nt = nthreads or max_threads()
+    dl = _as_c(delays, np.int32)
+    lib = _clib()
+    P = ctypes.POINTER
+    if y.dtype == np.float64:
+        ya = _as_c(y, np.float64)
+        lib.oracle_dedisperse_rows_f64(ya.ctypes.data_as(P(ctypes.c_double)), C, T,
+                                       dl.ctypes.data_as(P(ctypes.c_int32)), rows.shape[0],
+                                       rows.ctypes.data_as(P(ctypes.c_int32)), nout,
+                                       out.ctypes.data_as(P(ctypes.c_double)), nout, nt)
+    else:
+        ya = _as_c(y, np.float32)
+        lib.oracle_dedisperse_rows_f32(ya.ctypes.data_as(P(ctypes.c_float)), C, T,
+                                       dl.ctypes.data_as(P(ctypes.c_int32)), rows.shape[0],
+                                       rows.ctypes.data_as(P(ctypes.c_int32)), nout,
+                                       out.ctypes.data_as(P(ctypes.c_double)), nout, nt)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Detrending and normalisation, Sec. 2.2.3
+# --------------------------------------------------------------------------
+
+DEGENERATE_RTOL = 1e-9
+
+
+@dataclass
+class NormResult:
+    a: np.ndarray          # intercept per DM
+    b: np.ndarray          # slope per DM (per output sample)
+    sigma: np.ndarray      # std of the detrended series per DM
+    degenerate: np.ndarray # bool: sigma negligible, z set to 0
+    z: np.ndarray          # normalised series
+
+
+def normalise(D: np.ndarray) -> NormResult:
+    """Subtract the least-squares line a + b*t' from every DM's series
+    (t' = 0..N-1 local to this block of outputs), then divide by the
+    standard deviation of what remains.
+
+    Reading: population std (1/N); a series whose std is at most 1e-9 of its
+    RMS value (e.g. an exactly linear one) is degenerate and gets z = 0.
+    """
+    D = np.asarray(D, dtype=np.float64)
+    nd, N = D.shape
+    t = np.arange(N, dtype=np.float64)
+    if N == 0:
+        z = np.zeros_like(D)
+        zero = np.zeros(nd)
+        return NormResult(zero, zero.copy(), zero.copy(), np.ones(nd, bool), z)
+    tbar = (N - 1) / 2.0
+    tc = t - tbar
+    Stt = float(tc @ tc)
+    Dbar = D.mean(axis=1)
+    if Stt > 0:
+        b = ((D - Dbar[:, None]) @ tc) / Stt
+    else:
+        b = np.zeros(nd)
+    a = Dbar - b * tbar
+    r = D - a[:, None] - b[:, None] * t[None, :]
+    sigma = np.sqrt(np.mean(r * r, axis=1))
+    rms = np.sqrt(np.mean(D * D, axis=1))
+    degenerate = sigma <= DEGENERATE_RTOL * rms
+    z = np.zeros_like(D)
+    ok = ~degenerate
+    z[ok] = r[ok] / sigma[ok, None]
+    return NormResult(a, b, sigma, degenerate, z)
+
+
+# --------------------------------------------------------------------------
+# Event detection: n-sigma threshold, Sec. 2.3
+# --------------------------------------------------------------------------
+
+CANDIDATE_DTYPE = np.dtype([("dm_index", np.int32), ("pad", np.int32),
+                            ("sample", np.int64), ("snr", np.float32),
+                            ("dm", np.float32)])
+PEAK_DTYPE = np.dtype([("sample", np.int64), ("snr", np.float32), ("pad", np.int32)])
+
+
+def detect(z: np.ndarray, nsigma: float, sample0: int = 0,
+           dms: np.ndarray | None = None):
+    """(time, DM, intensity) triplets for every z > nsigma, in (DM, time)
+    order, plus the per-DM peak (largest z, earliest sample on ties).
+
+    Reading: one-sided strict threshold on the normalised series.
+    """
+    d, t = np.nonzero(z > nsigma)
+    cands = np.zeros(d.shape[0], dtype=CANDIDATE_DTYPE)
+    cands["dm_index"] = d
+    cands["sample"] = sample0 + t
+    cands["snr"] = z[d, t].astype(np.float32)
+    if dms is not None:
+        cands["dm"] = np.asarray(dms, dtype=np.float64)[d].astype(np.float32)
+    peaks = np.zeros(z.shape[0], dtype=PEAK_DTYPE)
+    if z.shape[1] > 0:
+        am = np.argmax(z, axis=1)
+        peaks["sample"] = sample0 + am
+        peaks["snr"] = z[np.arange(z.shape[0]), am].astype(np.float32)
+    margin = float(np.min(np.abs(z - nsigma))) if z.size else math.inf
+    return cands, peaks, margin
+
+
+# --------------------------------------------------------------------------
+# The whole single-shot step
+# --------------------------------------------------------------------------
+
+@dataclass
+class PlanDesc:
+    nchans: int
+    f_ch0_mhz: float
+    df_mhz: float
+    tsamp_s: float
+    ndms: int
+    dm_start: float
+    dm_step: float
+
+
+def run(x: np.ndarray, plan: PlanDesc, rfi: RfiParams | None, nsigma: float,
+        rows=None, nthreads: int | None = None) -> dict:
+    """Delay table -> RFI pass -> dedispersion -> normalisation -> detection.
+
+    With rfi None the stored values are dedispersed as they are.  With rows
+    given, only those DM rows are dedispersed, normalised and thresholded.
+    """
+    delays = delay_table(plan.nchans, plan.f_ch0_mhz, plan.df_mhz, plan.tsamp_s,
+                         plan.ndms, plan.dm_start, plan.dm_step)
+    smax = max_delay(delays)
+    T = x.shape[1]
+    nout = T - smax
+    res = {"delays": delays, "smax": smax, "nout": nout}
+    if rfi is not None:
+        r = rfi_clean(x, rfi)
+        res["rfi"] = r
+        y = r.y
+    else:
+        y = x
+    if rows is None:
+        D = dedisperse(y, delays, nout, nthreads)
+        idx = np.arange(plan.ndms)
+    else:
+        idx = np.asarray(rows)
+        D = dedisperse_rows(y, delays, idx, nout, nthreads)
+    nr = normalise(D)
+    dms = dm_trials(plan.ndms, plan.dm_start, plan.dm_step)[idx]
+    cands, peaks, margin = detect(nr.z, nsigma, 0, dms)
+    if rows is not None:
+        cands["dm_index"] = idx[cands["dm_index"]]
+    res.update(D=D, norm=nr, cands=cands, peaks=peaks, z_margin=margin, rows=idx)
+    return res

@@ -1,0 +1,88 @@
+"""Planted mistakes in the oracle must fail its pins.
+
+Each case rebuilds one oracle step with a plausible slip (a dropped term, a
+wrong sign or index, a transposed operand) and runs the same check that pins
+the real step; the check has to reject the mutant.  Everything runs on the
+CPU and touches only oracle code.
+"""
+import math
+
+import numpy as np
+
+import oracle
+from oracle import brute
+from paper_1307_5700_amd import synth
+
+
+def _delay_variants(p):
+    f = oracle.channel_freqs(p["nchans"], p["f_ch0_mhz"], p["df_mhz"])
+    dms = oracle.dm_trials(p["ndms"], p["dm_start"], p["dm_step"])
+    k = 4150.0
+    yield "truncate", np.floor((k * dms)[:, None] * (1 / f**2 - 1 / f.max()**2)[None, :] / p["tsamp_s"]).astype(np.int32)
+    yield "f_ref_bottom", np.floor((k * dms)[:, None] * np.abs(1 / f**2 - 1 / f.min()**2)[None, :] / p["tsamp_s"] + 0.5).astype(np.int32)
+    yield "ms_constant", np.floor((4.15 * dms)[:, None] * (1 / f**2 - 1 / f.max()**2)[None, :] / p["tsamp_s"] + 0.5).astype(np.int32)
+    yield "inverse_f", np.floor((k * dms)[:, None] * (1 / f - 1 / f.max())[None, :] / p["tsamp_s"] + 0.5).astype(np.int32)
+
+
+def test_delay_mutants_fail_exact_check():
+    p = synth.plain_single_beam().plan_kwargs()
+    exact = np.array(brute.delay_exact(**p)[0])
+    for name, s in _delay_variants(p):
+        assert not np.array_equal(s, exact), name
+
+
+def test_dedisperse_mutants_fail_brute_force():
+    rng = np.random.default_rng(5)
+    b = synth.tiny_beam(nchans=8, ndms=5, dm_step=2.0)
+    s = oracle.delay_table(**b.plan_kwargs())
+    y = rng.standard_normal((8, 64))
+    nout = 64 - int(s.max())
+    ref = np.array(brute.dedisperse_loops(y.tolist(), s.tolist(), nout))
+    mutants = {
+        "negative_shift": lambda: np.array([[sum(y[c][t + int(s.max()) - s[d][c]] for c in range(8))
+                                             for t in range(nout)] for d in range(5)]),
+        "reversed_channels": lambda: oracle.dedisperse(y, s[:, ::-1].copy(), nout),
+        "dropped_last_channel": lambda: oracle.dedisperse(y[:-1], s[:, :-1].copy(), nout),
+    }
+    for name, fn in mutants.items():
+        assert not np.allclose(fn(), ref), name
+
+
+def test_sigma_without_scale_factor_fails_noise_pin():
+    rng = np.random.default_rng(22)
+    C, T = 512, 8192
+    x = 2.5 * rng.standard_normal((C, T))
+    r = oracle.rfi_clean(x, oracle.RfiParams())
+    mutant = r.rmse                       # forgot sqrt(T*C/(C-p-1))
+    assert abs(r.sigma - 2.5) / 2.5 < 0.08
+    assert abs(mutant - 2.5) / 2.5 > 0.5
+
+
+def test_normalise_mutants_fail_invariants():
+    rng = np.random.default_rng(31)
+    N = 4000
+    D = rng.standard_normal((1, N)) * 3.0 + 5.0 + 0.002 * np.arange(N)[None, :]
+    t = np.arange(N)
+    good = oracle.normalise(D)
+    assert abs((good.z ** 2).mean() - 1) < 1e-10
+    # sample std instead of population std, and an uncentred time axis
+    r = D - good.a[:, None] - good.b[:, None] * t
+    z_sample_std = r / np.sqrt((r ** 2).sum() / (N - 1))
+    assert abs((z_sample_std ** 2).mean() - 1) > 1e-5
+    b_wrong = ((D - D.mean()) @ t) / (t @ t)                 # slope through the origin
+    z_wrong = (D - D.mean() - b_wrong * (t - t.mean()))
+    assert abs((z_wrong @ (t - t.mean()))[0]) > 1e-3
+
+
+def test_one_sided_spectrum_threshold_misses_gap():
+    """Reading the spectrum comparison as one-sided would miss a zeroed
+    broadband gap; the two-sided oracle catches it."""
+    f0, df = synth.band(256)
+    beam = synth.Beam(name="gap", nchans=256, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6,
+                      ndms=10, dm_start=0, dm_step=1, nsamps=8192, dtype="u8", seed=9,
+                      gaps=[synth.Gap(c0=0, nch=256, t0=4000, length=2)])
+    x = synth.render(beam, None)
+    r = oracle.rfi_clean(x, oracle.RfiParams())
+    assert r.spectrum_flags[4000] and r.spectrum_flags[4001]
+    one_sided = r.spectrum_means > oracle.RfiParams().k_spec * r.sigma / math.sqrt(256)
+    assert not one_sided[4000]
