@@ -1,0 +1,271 @@
+/*
+ * mbtp.h - C ABI of the MI355X multibeam transient hot path.
+ *
+ * One beam's channelised power (beam/channel/time order, Sec. 2.1) passes
+ * through the thresholding RFI pass (Sec. 2.2.1), brute-force incoherent
+ * dedispersion over a grid of trial DMs with the integer cold-plasma delays
+ * of Eq. (1) (Sec. 2.2.2), per-DM detrending and normalisation
+ * (Sec. 2.2.3) and the n-sigma event threshold that yields
+ * (time, DM, intensity) triplets (Sec. 2.3).
+ *
+ * Conventions shared by every call:
+ *  - Device pointers ("d_" prefix) are HIP device memory owned by the
+ *    caller.  Host pointers ("h_" prefix or plain structs) are host memory.
+ *    The library allocates device memory only inside *_create calls and
+ *    frees it in the matching *_destroy.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call that takes a stream only enqueues work on it and returns;
+ *    results are valid once the stream has reached that point.  Calls on
+ *    one plan from several streams are safe: a plan is immutable after
+ *    creation.  A beam (streaming state) or an RFI state buffer must be used
+ *    by one stream at a time.
+ *  - Filterbanks are x[c][t]: channel c's samples are contiguous in time,
+ *    row c starts at element c*ld.  The device pointer must be 16-byte
+ *    aligned and ld a multiple of 4 elements.
+ *  - Every call validates its arguments before enqueuing anything; on an
+ *    error nothing is enqueued, the call returns a non-zero mb_status and
+ *    mb_last_error() (per thread) describes it.  No C++ exception crosses
+ *    this interface.
+ *  - The plan, its delay table and all launches use the HIP device that is
+ *    current when dedisp_plan_create is called; later calls must be made
+ *    with that device current.
+ */
+#ifndef MBTP_H
+#define MBTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mb_status;
+enum {
+  MB_OK = 0,
+  MB_EINVAL = 1,     /* invalid argument or shape; nothing was enqueued   */
+  MB_ENOMEM = 2,     /* a create call could not allocate device memory    */
+  MB_EDEVICE = 3,    /* a HIP runtime call failed                          */
+  MB_ECAPACITY = 4,  /* more results than the caller's buffer holds        */
+  MB_EBUSY = 5       /* resource in use                                    */
+};
+
+/* Storage type of filterbank samples.  All are widened exactly to FP32 and
+ * accumulated in FP32 (u8: 0..255; f16: IEEE binary16; f32: binary32). */
+typedef int32_t mb_dtype;
+enum { MB_U8 = 0, MB_F16 = 1, MB_F32 = 2 };
+
+/* Factors of the thresholding RFI pass (Sec. 2.2.1).  Defaults in
+ * brackets; mb_rfi_defaults() fills them. */
+typedef struct {
+  int32_t poly_order;   /* p of the bandpass polynomial, 0..8 [3]           */
+  int32_t window;       /* W_c, chunk width in samples, multiple of 256 [256] */
+  double k_mask;        /* channel masking factor x RMSE of the fit [5]      */
+  double k_chan;        /* chunk-mean threshold in noise stds [5]            */
+  double k_spec;        /* spectrum-mean threshold in noise stds [5]         */
+  int32_t mask_passes;  /* fit-and-mask rounds before the final fit [1]      */
+  int32_t reserved;     /* must be 0                                         */
+} mb_rfi_params;
+
+/* Observing and survey parameters of one beam (Sec. 1.1, Sec. 2.2.2) and
+ * the factors of its RFI pass (Sec. 2.2.1), like the paper's one
+ * configuration file for all operating parameters.
+ * Channel c has centre frequency f_ch0_mhz + c*df_mhz (df may be negative).
+ * Trial DM d is dm_start + d*dm_step (pc cm^-3), d = 0..ndms-1. */
+typedef struct {
+  int32_t nchans;      /* C, 1..65535                                      */
+  int32_t ndms;        /* 1..65535                                         */
+  double f_ch0_mhz;    /* > 0                                              */
+  double df_mhz;       /* != 0, all channel centres > 0                    */
+  double tsamp_s;      /* sampling time > 0                                */
+  double dm_start;     /* >= 0                                             */
+  double dm_step;      /* >= 0                                             */
+  mb_dtype in_dtype;   /* storage type of the filterbanks executed        */
+  int32_t tile_hint;   /* 0: library's choice; k > 0: k-th compiled
+                          dedispersion tiling (results do not depend on it) */
+  mb_rfi_params rfi;   /* used by rfi_threshold                           */
+} mb_plan_desc;
+
+typedef struct {
+  int32_t nchans, ndms;
+  int32_t max_delay;    /* s_max: largest entry of the delay table        */
+  int32_t dm_block;     /* DMs per dedispersion workgroup (tiling info)   */
+  int32_t time_tile;    /* output samples per dedispersion workgroup      */
+  int32_t chan_block;   /* channels per LDS stage                         */
+  int64_t lds_bytes;    /* LDS per dedispersion workgroup                 */
+} mb_plan_info;
+
+/* Summary of one RFI pass, read back with rfi_report(). */
+typedef struct {
+  double sigma;           /* per-sample noise std implied by the fit RMSE    */
+  double rmse0;           /* RMSE of the first fit (masking criterion)       */
+  double rmse;            /* RMSE of the final fit                           */
+  double sum_fit;         /* sum over channels of the fitted bandpass        */
+  int64_t n_masked;       /* channels replaced by their neighbours' mean     */
+  int64_t n_chunk_flags;  /* chunks over threshold                           */
+  int64_t n_chunk_flags_ext; /* after extension to time-adjacent chunks      */
+  int64_t n_spectrum_flags;  /* spectra over threshold                       */
+  int64_t nsamps, nchunks;
+  int32_t error;          /* 0, or 1 when every channel got masked (then no
+                             sample is flagged and the fit is not usable)    */
+  int32_t reserved;
+} mb_rfi_report;
+
+/* Byte offsets of the arrays inside an RFI state buffer (for inspection). */
+typedef struct {
+  size_t total_bytes;
+  size_t fit_f64;          /* f[C], fitted bandpass (FP64)                  */
+  size_t bandpass_f64;     /* B[C], time-averaged bandpass (FP64)           */
+  size_t chunk_sum_f64;    /* M[C][J], sum of raw samples per chunk (FP64)  */
+  size_t chunk_flags_u8;   /* [C][J]: bit0 chunk over threshold, bit1 after
+                              extension to time-adjacent chunks             */
+  size_t spectrum_flags_u8;/* [T]: 1 where the spectrum was flagged         */
+  size_t masked_u8;        /* [C]: 1 where the channel was interpolated     */
+  int64_t nchunks;         /* J = ceil(T / W_c)                             */
+} mb_rfi_layout;
+
+/* Per-DM detrend line and scale (Sec. 2.2.3): for output sample t' of this
+ * block (0-based), z = (D[t'] - a - b*t') / sigma.  degenerate != 0 when
+ * sigma <= 1e-9 * rms(D) (e.g. an exactly linear series); then z = 0. */
+typedef struct {
+  double a, b, sigma;
+  int32_t degenerate;
+  int32_t reserved;
+} mb_norm;
+
+/* One (time, DM, intensity) triplet (Sec. 2.3). */
+typedef struct {
+  int32_t dm_index;
+  int32_t reserved;
+  int64_t sample;   /* absolute sample index of the dedispersed series   */
+  float snr;        /* z, the normalised intensity                       */
+  float dm;         /* trial DM value, pc cm^-3                          */
+} mb_candidate;
+
+/* Largest z of one DM row (earliest sample on ties). */
+typedef struct {
+  int64_t sample;
+  float snr;
+  int32_t reserved;
+} mb_peak;
+
+/* Streaming position of a beam after an execute (host-known). */
+typedef struct {
+  int64_t nout;      /* dedispersed samples produced per DM by this call   */
+  int64_t sample0;   /* absolute index of the first of them                */
+} mb_exec_info;
+
+typedef struct mb_plan mb_plan;
+typedef struct mb_beam mb_beam;
+
+/* ---- plan ------------------------------------------------------------- */
+
+/* Builds the integer delay table of Eq. (1) on the host in FP64,
+ *   s[d][c] = floor(4150 * DM_d * (f_c^-2 - f_ref^-2) / tsamp + 1/2),
+ * 4150 s MHz^2 being the paper's 4.15e6 ms and f_ref the highest channel
+ * centre, copies it to the current device and picks the dedispersion
+ * tiling.  *out receives a plan to release with dedisp_plan_destroy.
+ * Errors: MB_EINVAL (bad descriptor), MB_ENOMEM, MB_EDEVICE. */
+mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out);
+mb_status dedisp_plan_destroy(mb_plan* plan);
+mb_status dedisp_plan_info(const mb_plan* plan, mb_plan_info* info);
+/* Copies the delay table, int32 [ndms][nchans] row-major, to host memory. */
+mb_status dedisp_plan_delays(const mb_plan* plan, int32_t* h_delays);
+
+/* ---- RFI thresholding (Sec. 2.2.1) ------------------------------------ */
+
+void mb_rfi_defaults(mb_rfi_params* p);
+
+/* Size and layout of the caller-owned device buffer that holds one RFI
+ * pass's statistics, fitted bandpass and flags for nsamps samples. */
+mb_status rfi_state_layout(const mb_plan* plan, int64_t nsamps, mb_rfi_layout* layout);
+
+/* Runs the three stages of Sec. 2.2.1, with the plan's RFI factors, on d_in
+ * (plan's in_dtype, [C][nsamps] with leading dimension ld): per-channel and per-chunk sums and per-sample
+ * spectrum sums in one HBM pass (FP64 accumulation), the bandpass fit with
+ * channel masking on one workgroup, chunk flags with extension to the
+ * adjacent chunks, and spectrum flags.  The input is not modified; the
+ * cleaning is applied on the fly by dedisp_execute.  d_state must be at
+ * least layout.total_bytes and 256-byte aligned; its previous contents are
+ * overwritten.  Errors: MB_EINVAL (shape, params, small state buffer). */
+mb_status rfi_threshold(const mb_plan* plan, const void* d_in, int64_t nsamps,
+                        int64_t ld, void* d_state, size_t state_bytes, void* stream);
+
+/* Waits for the stream and copies the pass summary to *h_report. */
+mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_report,
+                     void* stream);
+
+/* ---- dedispersion (Sec. 2.2.2) + normalisation (Sec. 2.2.3) ------------ */
+
+/* Dedisperses d_in into d_out (FP32, [ndms][ld_out]):
+ *   D[d][t] = sum_c y[c][t + s[d][c]],
+ * y being the stored sample widened to FP32, or, when d_rfi_state is not
+ * NULL (the state rfi_threshold wrote for this same d_in and nsamps), the
+ * sample minus the fitted bandpass f_c rounded to FP32, or 0 where its chunk
+ * or spectrum was flagged.
+ * Sums are FP32, channels accumulated in ascending order in blocks of 32
+ * (a fixed order, so results do not depend on the tiling).
+ *
+ * beam == NULL: single shot over nsamps samples; nout = nsamps - s_max
+ * outputs per DM (MB_EINVAL if nsamps <= s_max).
+ * beam != NULL: the chunk continues the beam's stream; nsamps must be a
+ * multiple of 4 (MB_EINVAL otherwise).  The beam keeps the last s_max
+ * cleaned samples of every channel on the device, so the chunk
+ * yields nout = min(seen, s_max) + nsamps - s_max outputs (0 until s_max
+ * samples have been seen), starting at absolute sample
+ * max(0, seen - s_max), "seen" counting the samples before this chunk.
+ *
+ * d_norm (nullable, [ndms]) receives each DM's detrend line and scale over
+ * the outputs of this call (Sec. 2.2.3).  info (nullable, host) receives
+ * nout and sample0.  ld_out >= nout.  Errors: MB_EINVAL. */
+mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in,
+                         int64_t nsamps, int64_t ld, const void* d_rfi_state,
+                         float* d_out, int64_t ld_out, mb_norm* d_norm,
+                         mb_exec_info* info, void* stream);
+
+/* Detrend line and scale of every row of a dedispersed plane (Sec. 2.2.3),
+ * exactly as dedisp_execute forms them: d_out [ndms][ld_out] FP32 with nout
+ * samples per row (16-byte aligned, ld_out % 4 == 0), d_norm [ndms]. */
+mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout,
+                           int64_t ld_out, mb_norm* d_norm, void* stream);
+
+/* ---- streaming state --------------------------------------------------- */
+
+/* A beam's device-resident overlap ring: the last R cleaned FP32 samples of
+ * every channel, R = s_max rounded up to a multiple of 4, plus the absolute
+ * sample count.  Allocates nchans * R * 4 bytes on the plan's device. */
+mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out);
+mb_status dedisp_beam_destroy(mb_beam* beam);
+/* Forgets the stream history (the next chunk is the first). Host-only. */
+mb_status dedisp_beam_reset(mb_beam* beam);
+mb_status dedisp_beam_position(const mb_beam* beam, int64_t* seen);
+
+/* ---- event detection (Sec. 2.3) ---------------------------------------- */
+
+/* Bytes of caller-owned device workspace detect_candidates needs. */
+mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes);
+
+/* Thresholds z = (D[d][t] - a_d - b_d*t) / sigma_d > nsigma (strict, FP64)
+ * over d_out [ndms][ld_out], t < nout, with d_norm from dedisp_execute.
+ * Writes candidates in (dm_index, sample) order, sample = sample0 + t:
+ * the first min(count, capacity) to d_cands, the true count to *d_count
+ * (device int64).  More than capacity is not an error at enqueue time: the
+ * caller compares *d_count with capacity once the stream has run.
+ * d_peaks (nullable, [ndms]) receives each row's largest z and its earliest
+ * sample.  d_work: at least detect_workspace_size bytes, 256-byte aligned. */
+mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nout,
+                            int64_t ld_out, const mb_norm* d_norm, int64_t sample0,
+                            double nsigma, mb_candidate* d_cands, int64_t capacity,
+                            int64_t* d_count, mb_peak* d_peaks, void* d_work,
+                            size_t work_bytes, void* stream);
+
+/* ---- errors ------------------------------------------------------------ */
+
+const char* mb_status_str(mb_status s);
+/* Description of the last error on the calling thread ("" if none). */
+const char* mb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBTP_H */

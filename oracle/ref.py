@@ -425,6 +425,37 @@ def detect(z: np.ndarray, nsigma: float, sample0: int = 0,
 
 
 # --------------------------------------------------------------------------
+# Streaming: chunks of one beam processed in turn (Sec. 2.2.1 cleans each
+# iteration's buffer with its own statistics; Sec. 3's shift buffer carries
+# the samples that later outputs still need across iterations)
+# --------------------------------------------------------------------------
+
+def stream_outputs(chunks, delays: np.ndarray, rfi: RfiParams | None):
+    """Dedispersed outputs produced after each chunk of a stream.
+
+    Every chunk is cleaned with its own RFI statistics; the cleaned chunks
+    are concatenated and dedispersed as one series.  After chunk k, whose
+    first sample has absolute index a_k, the outputs with absolute index in
+    [max(0, a_k - s_max), a_k + L_k - s_max) are complete.  Returns a list of
+    (sample0, D block) per chunk.
+    """
+    smax = max_delay(delays)
+    ys = []
+    for x in chunks:
+        ys.append(rfi_clean(x, rfi).y if rfi is not None else np.asarray(x).astype(np.float64))
+    y = np.concatenate(ys, axis=1)
+    D = dedisperse(y, delays) if y.shape[1] > smax else np.zeros((delays.shape[0], 0))
+    out = []
+    a = 0
+    for x in chunks:
+        L_ = x.shape[1]
+        lo, hi = max(0, a - smax), max(0, a + L_ - smax)
+        out.append((lo, D[:, lo:hi]))
+        a += L_
+    return out
+
+
+# --------------------------------------------------------------------------
 # The whole single-shot step
 # --------------------------------------------------------------------------
 

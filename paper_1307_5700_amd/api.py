@@ -1,0 +1,255 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Device buffers are torch tensors on the plan's GPU; every step of the path
+runs in the library's HIP kernels.  Calls are enqueued on torch's current
+stream unless a stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+NORM_DTYPE = np.dtype([("a", "<f8"), ("b", "<f8"), ("sigma", "<f8"),
+                       ("degenerate", "<i4"), ("reserved", "<i4")])
+CANDIDATE_DTYPE = np.dtype([("dm_index", "<i4"), ("reserved", "<i4"), ("sample", "<i8"),
+                            ("snr", "<f4"), ("dm", "<f4")])
+PEAK_DTYPE = np.dtype([("sample", "<i8"), ("snr", "<f4"), ("reserved", "<i4")])
+TORCH_DTYPES = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32}
+
+
+@dataclass
+class RfiConfig:
+    """Factors of the RFI pass (Sec. 2.2.1); see include/mbtp.h."""
+    poly_order: int = 3
+    window: int = 256
+    k_mask: float = 5.0
+    k_chan: float = 5.0
+    k_spec: float = 5.0
+    mask_passes: int = 1
+
+    def to_c(self) -> L.RfiParams:
+        return L.RfiParams(self.poly_order, self.window, self.k_mask, self.k_chan, self.k_spec,
+                           self.mask_passes, 0)
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    """A byte buffer whose start is 256-byte aligned."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + int(nbytes)]
+
+
+class Plan:
+    """Delay table + tiling for one beam's observing/survey parameters."""
+
+    def __init__(self, nchans, f_ch0_mhz, df_mhz, tsamp_s, ndms, dm_start, dm_step,
+                 dtype: str = "f32", rfi: RfiConfig | None = None, tile_hint: int = 0,
+                 device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.dtype = dtype
+        self.rfi_config = rfi or RfiConfig()
+        desc = L.PlanDesc(int(nchans), int(ndms), float(f_ch0_mhz), float(df_mhz), float(tsamp_s),
+                          float(dm_start), float(dm_step), L.DTYPES[dtype], int(tile_hint),
+                          self.rfi_config.to_c())
+        self._desc = desc
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().dedisp_plan_create(ctypes.byref(desc), ctypes.byref(h)),
+                    "dedisp_plan_create")
+        self._h = h
+        info = L.PlanInfo()
+        L.check(L.lib().dedisp_plan_info(h, ctypes.byref(info)), "dedisp_plan_info")
+        self.nchans, self.ndms = info.nchans, info.ndms
+        self.max_delay = info.max_delay
+        self.tiling = dict(dm_block=info.dm_block, time_tile=info.time_tile,
+                           chan_block=info.chan_block, lds_bytes=info.lds_bytes)
+        self.dm_start, self.dm_step = float(dm_start), float(dm_step)
+        ws = ctypes.c_size_t()
+        L.check(L.lib().detect_workspace_size(h, ctypes.byref(ws)), "detect_workspace_size")
+        self.detect_work_bytes = ws.value
+
+    @classmethod
+    def from_beam(cls, beam, rfi: RfiConfig | None = None, tile_hint: int = 0, device=None):
+        return cls(dtype=beam.dtype, rfi=rfi, tile_hint=tile_hint, device=device,
+                   **beam.plan_kwargs())
+
+    # ---- plan ----
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.ndms, self.nchans), dtype=np.int32)
+        L.check(L.lib().dedisp_plan_delays(self._h, out.ctypes.data_as(ctypes.c_void_p)),
+                "dedisp_plan_delays")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().dedisp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers ----
+    def _check_input(self, x: torch.Tensor):
+        if x.device != self.device or x.dim() != 2 or x.shape[0] != self.nchans or x.stride(1) != 1:
+            raise ValueError("input must be a [nchans, T] tensor with unit time stride on the plan's GPU")
+        if x.dtype != TORCH_DTYPES[self.dtype]:
+            raise ValueError(f"input dtype {x.dtype} does not match the plan ({self.dtype})")
+        return x.shape[1], x.stride(0)
+
+    def alloc_output(self, nout: int) -> torch.Tensor:
+        ld = (int(nout) + 3) // 4 * 4
+        return torch.empty((self.ndms, max(ld, 4)), dtype=torch.float32, device=self.device)
+
+    def alloc_norm(self) -> torch.Tensor:
+        return torch.empty((self.ndms, L.NORM_BYTES // 8), dtype=torch.float64, device=self.device)
+
+    # ---- RFI (Sec. 2.2.1) ----
+    def rfi_layout(self, nsamps: int) -> L.RfiLayout:
+        lay = L.RfiLayout()
+        L.check(L.lib().rfi_state_layout(self._h, int(nsamps), ctypes.byref(lay)), "rfi_state_layout")
+        return lay
+
+    def alloc_rfi_state(self, nsamps: int) -> torch.Tensor:
+        return _alloc(self.rfi_layout(nsamps).total_bytes, self.device)
+
+    def rfi_threshold(self, x: torch.Tensor, state: torch.Tensor | None = None, stream=None):
+        T, ld = self._check_input(x)
+        if state is None:
+            state = self.alloc_rfi_state(T)
+        L.check(L.lib().rfi_threshold(self._h, _ptr(x), T, ld, _ptr(state), state.numel(),
+                                      _stream_ptr(stream)), "rfi_threshold")
+        return state
+
+    def rfi_report(self, state: torch.Tensor, stream=None) -> dict:
+        rep = L.RfiReport()
+        L.check(L.lib().rfi_report(self._h, _ptr(state), ctypes.byref(rep), _stream_ptr(stream)),
+                "rfi_report")
+        return {f: getattr(rep, f) for f, _ in L.RfiReport._fields_ if f != "reserved"}
+
+    def rfi_arrays(self, state: torch.Tensor, nsamps: int) -> dict:
+        """Host copies of the fitted bandpass and flags held in an RFI state."""
+        lay = self.rfi_layout(nsamps)
+        h = state.cpu().numpy()
+        C, J = self.nchans, lay.nchunks
+
+        def view(off, dtype, shape):
+            n = int(np.prod(shape)) * np.dtype(dtype).itemsize
+            return h[off:off + n].view(dtype).reshape(shape).copy()
+
+        flags = view(lay.chunk_flags_u8, np.uint8, (C, J))
+        return {"fit": view(lay.fit_f64, np.float64, (C,)),
+                "bandpass_interp": view(lay.bandpass_f64, np.float64, (C,)),
+                "chunk_sum": view(lay.chunk_sum_f64, np.float64, (C, J)),
+                "chunk_flags": (flags & 1).astype(bool),
+                "chunk_flags_ext": (flags & 2).astype(bool),
+                "spectrum_flags": view(lay.spectrum_flags_u8, np.uint8, (nsamps,)).astype(bool),
+                "masked": view(lay.masked_u8, np.uint8, (C,)).astype(bool)}
+
+    # ---- dedispersion (Sec. 2.2.2) + normalisation (Sec. 2.2.3) ----
+    def execute(self, x: torch.Tensor, rfi_state: torch.Tensor | None = None,
+                out: torch.Tensor | None = None, norm: torch.Tensor | None | bool = True,
+                beam: "Beam | None" = None, stream=None):
+        """Returns (out, norm, nout, sample0)."""
+        T, ld = self._check_input(x)
+        if out is None:
+            seen = beam.position() if beam is not None else 0
+            v = min(seen, self.max_delay) if beam is not None else 0
+            out = self.alloc_output(max(v + T - self.max_delay, 0))
+        if norm is True:
+            norm = self.alloc_norm()
+        elif norm is False:
+            norm = None
+        info = L.ExecInfo()
+        L.check(L.lib().dedisp_execute(self._h, beam._h if beam is not None else None, _ptr(x), T, ld,
+                                       _ptr(rfi_state), _ptr(out), out.stride(0), _ptr(norm),
+                                       ctypes.byref(info), _stream_ptr(stream)), "dedisp_execute")
+        return out, norm, info.nout, info.sample0
+
+    def normalise(self, out: torch.Tensor, nout: int, norm: torch.Tensor | None = None, stream=None):
+        """Detrend line and scale of each row of a dedispersed plane."""
+        norm = self.alloc_norm() if norm is None else norm
+        L.check(L.lib().dedisp_normalise(self._h, _ptr(out), int(nout), out.stride(0), _ptr(norm),
+                                         _stream_ptr(stream)), "dedisp_normalise")
+        return norm
+
+    # ---- detection (Sec. 2.3) ----
+    def alloc_detect(self, capacity: int):
+        cands = torch.empty(max(int(capacity), 1) * L.CANDIDATE_BYTES, dtype=torch.uint8, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        peaks = torch.empty(self.ndms * L.PEAK_BYTES, dtype=torch.uint8, device=self.device)
+        work = _alloc(self.detect_work_bytes, self.device)
+        return cands, count, peaks, work
+
+    def detect(self, out: torch.Tensor, nout: int, norm: torch.Tensor, nsigma: float,
+               sample0: int = 0, capacity: int = 1 << 16, buffers=None, stream=None):
+        """Enqueues detection; returns the device buffers (cands, count, peaks, work)."""
+        cands, count, peaks, work = buffers if buffers is not None else self.alloc_detect(capacity)
+        cap = cands.numel() // L.CANDIDATE_BYTES
+        L.check(L.lib().detect_candidates(self._h, _ptr(out), int(nout), out.stride(0), _ptr(norm),
+                                          int(sample0), float(nsigma), _ptr(cands), cap, _ptr(count),
+                                          _ptr(peaks), _ptr(work), work.numel(), _stream_ptr(stream)),
+                "detect_candidates")
+        return cands, count, peaks, work
+
+    @staticmethod
+    def candidates_to_host(cands: torch.Tensor, count: torch.Tensor):
+        n = int(count.item())
+        cap = cands.numel() // L.CANDIDATE_BYTES
+        arr = cands[:min(n, cap) * L.CANDIDATE_BYTES].cpu().numpy().view(CANDIDATE_DTYPE)
+        return arr, n
+
+    @staticmethod
+    def norm_to_host(norm: torch.Tensor) -> np.ndarray:
+        return norm.cpu().numpy().reshape(-1).view(NORM_DTYPE)
+
+    @staticmethod
+    def peaks_to_host(peaks: torch.Tensor) -> np.ndarray:
+        return peaks.cpu().numpy().view(PEAK_DTYPE)
+
+
+class Beam:
+    """Device-resident streaming state of one beam (overlap ring)."""
+
+    def __init__(self, plan: Plan):
+        h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            L.check(L.lib().dedisp_beam_create(plan._h, ctypes.byref(h)), "dedisp_beam_create")
+        self._h = h
+        self.plan = plan
+
+    def position(self) -> int:
+        v = ctypes.c_int64()
+        L.check(L.lib().dedisp_beam_position(self._h, ctypes.byref(v)), "dedisp_beam_position")
+        return v.value
+
+    def reset(self):
+        L.check(L.lib().dedisp_beam_reset(self._h), "dedisp_beam_reset")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().dedisp_beam_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

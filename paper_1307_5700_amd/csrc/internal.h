@@ -1,0 +1,159 @@
+// Internal interface between the host runtime (mbtp.cpp) and the HIP kernel
+// files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mbtp {
+
+// Samples of one wave-span of the statistics pass: a wave covers 256
+// consecutive samples of one channel, 4 per lane.
+constexpr int kSpan = 256;
+// Channels summed into one FP32 partial before it is added to the running
+// total of a dedispersed sample; a fixed constant so every tiling, batch and
+// replay adds in the same order.
+constexpr int kAccGroup = 32;
+
+// Header at offset 0 of an RFI state buffer (256 bytes reserved).
+struct RfiHeader {
+  double sigma;       // per-sample noise std implied by the fit RMSE
+  double rmse0;       // RMSE of the first fit
+  double rmse;        // RMSE of the final fit
+  double sum_fit;     // sum_c f_c
+  double thr_spec;    // k_spec * sigma / sqrt(C)
+  double k_chan;      // chunk threshold factor (chunk thr = k_chan*sigma/sqrt(L_j))
+  unsigned long long n_masked, n_chunk, n_chunk_ext, n_spec;
+  int64_t nsamps, nchunks;
+  int32_t error;      // 1: every channel masked
+  int32_t pad;
+};
+static_assert(sizeof(RfiHeader) <= 256, "header too large");
+
+// Geometry and byte offsets of an RFI state buffer for C channels, T
+// samples and chunk width W (a multiple of kSpan).
+struct RfiGeom {
+  int64_t C, T, W, J, nspans, CG, ngroups;
+  size_t off_hdr, off_fit, off_fit32, off_bsum, off_binterp, off_span, off_chunk, off_spart;
+  size_t off_flags, off_lcount, off_list, off_gflags, off_masked, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline RfiGeom rfi_geometry(int64_t C, int64_t T, int64_t W) {
+  RfiGeom g;
+  g.C = C; g.T = T; g.W = W;
+  g.J = (T + W - 1) / W;
+  g.nspans = (T + kSpan - 1) / kSpan;
+  // channels per statistics workgroup: enough workgroups to fill the chip,
+  // few enough partial spectrum sums to keep the second pass cheap
+  int64_t cg = 64;
+  while (cg < 512 && (C + cg - 1) / cg > 8 && g.nspans * ((C + 2 * cg - 1) / (2 * cg)) >= 2048) cg *= 2;
+  g.CG = cg;
+  g.ngroups = (C + cg - 1) / cg;
+  size_t o = 0;
+  g.off_hdr = o;      o = align256(o + 256);
+  g.off_fit = o;      o = align256(o + sizeof(double) * C);
+  g.off_fit32 = o;    o = align256(o + sizeof(float) * C);
+  g.off_bsum = o;     o = align256(o + sizeof(double) * C);
+  g.off_binterp = o;  o = align256(o + sizeof(double) * C);
+  g.off_span = o;     o = align256(o + sizeof(double) * C * g.nspans);
+  g.off_chunk = o;    o = align256(o + sizeof(double) * C * g.J);
+  g.off_spart = o;    o = align256(o + sizeof(double) * g.ngroups * T);
+  g.off_flags = o;    o = align256(o + size_t(C) * g.J);
+  g.off_lcount = o;   o = align256(o + sizeof(int32_t) * g.J);
+  g.off_list = o;     o = align256(o + sizeof(int32_t) * C * g.J);
+  g.off_gflags = o;   o = align256(o + size_t(T));
+  g.off_masked = o;   o = align256(o + size_t(C));
+  g.total = o;
+  return g;
+}
+
+struct RfiParamsDev {
+  int32_t p, W, mask_passes;
+  double k_mask, k_chan, k_spec;
+};
+
+hipError_t launch_rfi(int dtype, const void* x, int64_t ld, const RfiGeom& g,
+                      const RfiParamsDev& prm, char* state, hipStream_t s);
+
+// Cleaning applied while staging samples for dedispersion.
+struct CleanView {
+  const double* fit;         // f[C]
+  const uint8_t* cflags;     // [C][J], bit1 = flagged after extension
+  const uint8_t* gflags;     // [T]
+  int64_t J;
+  uint32_t W;
+  int32_t wshift;            // log2(W) when W is a power of two, else -1
+};
+
+// Everything one dedispersion launch needs.
+//
+// Virtual input of a launch: the v ring samples that precede the chunk, then
+// the chunk's L samples (v, the ring length R and the ring position of virtual
+// sample 0 are multiples of 4, so every aligned quad of virtual samples lies
+// wholly in the ring or wholly in the chunk).  Output j of this launch is the
+// dedispersed sample at virtual index phase + j.
+struct DedispArgs {
+  const void* x;             // chunk [C][ld], L samples
+  int64_t ld, L;
+  const float* ring;         // [C][R] circular (stream mode) or null
+  int64_t R;                 // ring length, multiple of 4
+  int64_t ring_valid;        // v: ring samples preceding the chunk
+  int64_t ring_p0;           // ring position of virtual sample 0
+  int64_t phase;             // virtual index of output 0
+  const int32_t* delays;     // [ndms][C]
+  int32_t C, ndms;
+  int64_t nout;
+  float* out;                // [ndms][ld_out]
+  int64_t ld_out;
+  CleanView clean;
+  int32_t n_dblocks, n_ttiles;
+  int32_t rs;                // LDS copy length in floats (multiple of 4)
+  int32_t relb_ld;           // row stride of the relb table (channels rounded up to 4)
+};
+
+struct Tiling {
+  int G, Q, BC;   // DMs per wave, float4 groups per lane, channels per LDS stage
+  int BD() const { return 4 * G; }
+  int BT() const { return 256 * Q; }
+};
+
+// Quads of staged samples each thread prefetches per channel block.
+constexpr int kStageQuads = 4;
+
+// Variants compiled into the library.
+int n_tilings();
+Tiling tiling_at(int i);
+
+// Per-(DM, channel) LDS byte offsets of a tiling (see dedisp.hip).
+hipError_t launch_relb(const int32_t* delays, int32_t C, int32_t ndms, int32_t BD, int32_t RS,
+                       int32_t ldr, int32_t* relb, hipStream_t s);
+
+hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, const DedispArgs& a,
+                         const int32_t* relb, const float* fit32, size_t lds_bytes,
+                         hipStream_t s);
+
+// Writes the chunk's last min(L, R) cleaned samples into the ring.
+hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, int64_t L,
+                              int32_t C, const CleanView& cv, const float* fit32, float* ring,
+                              int64_t R, int64_t seen, hipStream_t s);
+
+struct NormDev { double a, b, sigma; int32_t degenerate, reserved; };
+struct CandDev { int32_t dm_index, reserved; int64_t sample; float snr, dm; };
+struct PeakDev { int64_t sample; float snr; int32_t reserved; };
+
+hipError_t launch_norm(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
+                       NormDev* norm, hipStream_t s);
+
+hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
+                         const NormDev* norm, int64_t sample0, double nsigma,
+                         double dm_start, double dm_step, CandDev* cands, int64_t capacity,
+                         int64_t* d_count, PeakDev* peaks, void* work, hipStream_t s);
+
+inline size_t detect_work_bytes(int32_t ndms) {
+  return align256(sizeof(int64_t) * 2 * (size_t(ndms) + 1));
+}
+
+}  // namespace mbtp

@@ -1,0 +1,511 @@
+// Host runtime behind the C ABI of include/mbtp.h: argument validation, the
+// FP64 delay table of Eq. (1), the choice of dedispersion tiling, device
+// memory owned by plans and beams, and the launch sequence of each call.
+//
+// Compiled with -ffp-contract=off: the delay table is formed with plain
+// IEEE FP64 multiplies, divides and adds, in the order written.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mbtp.h"
+#include "internal.h"
+
+using namespace mbtp;
+
+namespace {
+
+thread_local std::string g_err;
+
+mb_status fail(mb_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+mb_status ok() {
+  g_err.clear();
+  return MB_OK;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(MB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+// Eq. (1) with k = 4.15e6 ms MHz^2 = 4150 s MHz^2, f_ref the highest channel
+// centre, rounded to the nearest sample (halves up).
+constexpr double kDispersionS = 4150.0;
+
+void build_delays(const mb_plan_desc& d, std::vector<int32_t>& out, int32_t& smax) {
+  const int C = d.nchans, N = d.ndms;
+  std::vector<double> f(C);
+  double fref = -1.0;
+  for (int c = 0; c < C; ++c) {
+    f[c] = d.f_ch0_mhz + (double)c * d.df_mhz;
+    if (f[c] > fref) fref = f[c];
+  }
+  std::vector<double> inv(C);
+  const double iref = 1.0 / (fref * fref);
+  for (int c = 0; c < C; ++c) inv[c] = 1.0 / (f[c] * f[c]) - iref;
+  out.assign((size_t)N * C, 0);
+  smax = 0;
+  for (int k = 0; k < N; ++k) {
+    const double dm = d.dm_start + (double)k * d.dm_step;
+    const double kd = kDispersionS * dm;
+    for (int c = 0; c < C; ++c) {
+      const double v = kd * inv[c] / d.tsamp_s;
+      const int32_t s = (int32_t)floor(v + 0.5);
+      out[(size_t)k * C + c] = s;
+      if (s > smax) smax = s;
+    }
+  }
+}
+
+bool check_aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int dtype_bytes(int dt) { return dt == MB_U8 ? 1 : (dt == MB_F16 ? 2 : 4); }
+
+}  // namespace
+
+struct mb_plan {
+  mb_plan_desc desc;
+  int device = 0;
+  int32_t smax = 0;
+  std::vector<int32_t> h_delays;
+  int32_t* d_delays = nullptr;
+  int32_t* d_relb = nullptr;
+  Tiling tiling{8, 2, 4};
+  int rs = 0;
+  size_t lds = 0;
+  int n_dblocks = 0;
+  int relb_ld = 0;
+};
+
+struct mb_beam {
+  const mb_plan* plan = nullptr;
+  float* d_ring = nullptr;
+  int64_t R = 0;
+  int64_t seen = 0;
+};
+
+namespace {
+
+// Largest spread s[dlast][c] - s[d0][c] over DM blocks of size BD.
+int32_t span_max(const mb_plan& p, int BD) {
+  const int C = p.desc.nchans, N = p.desc.ndms;
+  int32_t m = 0;
+  for (int d0 = 0; d0 < N; d0 += BD) {
+    const int dl = (d0 + BD < N ? d0 + BD : N) - 1;
+    for (int c = 0; c < C; ++c) {
+      const int32_t s = p.h_delays[(size_t)dl * C + c] - p.h_delays[(size_t)d0 * C + c];
+      if (s > m) m = s;
+    }
+  }
+  return m;
+}
+
+constexpr size_t kMaxLds = 64 * 1024;
+
+// LDS copy length: the largest window start (span + 3, rounded down to 4)
+// plus the tile, plus the quad read after the last one.
+void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
+  const int sp = span_max(p, t.BD());
+  rs = (t.BT() + sp + 7 + 3) & ~3;
+  // four shifted copies per channel, then the block's [BC][BD] offsets
+  lds = (size_t)t.BC * 4 * rs * sizeof(float) + (size_t)t.BC * t.BD() * sizeof(int32_t);
+}
+
+// A tiling fits when its LDS fits and each lane's prefetch registers cover
+// its share of a channel block.
+bool tiling_fits(const Tiling& t, int rs, size_t lds) {
+  const int rows_per_wave = t.BC / 4;
+  const int quads_per_lane = ((rs / 4) + 63) / 64;
+  return lds <= kMaxLds && rows_per_wave * quads_per_lane <= kStageQuads;
+}
+
+mb_status choose_tiling(mb_plan& p) {
+  const int n = n_tilings();
+  int pick = -1;
+  if (p.desc.tile_hint > 0) {
+    if (p.desc.tile_hint > n) return fail(MB_EINVAL, "tile_hint %d out of range 1..%d", p.desc.tile_hint, n);
+    pick = p.desc.tile_hint - 1;
+    int rs; size_t lds;
+    tiling_geometry(p, tiling_at(pick), rs, lds);
+    if (!tiling_fits(tiling_at(pick), rs, lds))
+      return fail(MB_EINVAL, "tiling %d does not fit this plan (LDS %zu bytes, row %d)", p.desc.tile_hint, lds, rs);
+  } else {
+    // preference order of the compiled list; the first that fits in LDS
+    for (int i = 0; i < n && pick < 0; ++i) {
+      int rs; size_t lds;
+      tiling_geometry(p, tiling_at(i), rs, lds);
+      if (tiling_fits(tiling_at(i), rs, lds)) pick = i;
+    }
+    if (pick < 0) return fail(MB_EINVAL, "the DM step is too coarse for the compiled tilings (LDS)");
+  }
+  p.tiling = tiling_at(pick);
+  tiling_geometry(p, p.tiling, p.rs, p.lds);
+  p.n_dblocks = (p.desc.ndms + p.tiling.BD() - 1) / p.tiling.BD();
+  return MB_OK;
+}
+
+mb_status validate_rfi(const mb_rfi_params& r, int C) {
+  if (r.poly_order < 0 || r.poly_order > 8) return fail(MB_EINVAL, "rfi.poly_order %d not in 0..8", r.poly_order);
+  if (r.window <= 0 || r.window % kSpan != 0)
+    return fail(MB_EINVAL, "rfi.window %d must be a positive multiple of %d", r.window, kSpan);
+  if (!(r.k_mask > 0) || !(r.k_chan > 0) || !(r.k_spec > 0))
+    return fail(MB_EINVAL, "rfi threshold factors must be positive");
+  if (r.mask_passes < 1 || r.mask_passes > 16) return fail(MB_EINVAL, "rfi.mask_passes %d not in 1..16", r.mask_passes);
+  if (r.reserved != 0) return fail(MB_EINVAL, "rfi.reserved must be 0");
+  (void)C;
+  return MB_OK;
+}
+
+mb_status validate_input(const mb_plan* plan, const void* d_in, int64_t nsamps, int64_t ld) {
+  if (!plan) return fail(MB_EINVAL, "plan is NULL");
+  if (!d_in) return fail(MB_EINVAL, "input pointer is NULL");
+  if (!check_aligned(d_in, 16)) return fail(MB_EINVAL, "input pointer must be 16-byte aligned");
+  if (nsamps < 1) return fail(MB_EINVAL, "nsamps must be >= 1");
+  if (nsamps > INT32_MAX) return fail(MB_EINVAL, "nsamps must be < 2^31");
+  if (ld < nsamps || ld % 4 != 0) return fail(MB_EINVAL, "ld (%lld) must be >= nsamps and a multiple of 4", (long long)ld);
+  return MB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mb_status_str(mb_status s) {
+  switch (s) {
+    case MB_OK: return "ok";
+    case MB_EINVAL: return "invalid argument";
+    case MB_ENOMEM: return "out of device memory";
+    case MB_EDEVICE: return "HIP runtime error";
+    case MB_ECAPACITY: return "capacity exceeded";
+    case MB_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+const char* mb_last_error(void) { return g_err.c_str(); }
+
+void mb_rfi_defaults(mb_rfi_params* p) {
+  if (!p) return;
+  p->poly_order = 3;
+  p->window = 256;
+  p->k_mask = 5.0;
+  p->k_chan = 5.0;
+  p->k_spec = 5.0;
+  p->mask_passes = 1;
+  p->reserved = 0;
+}
+
+mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
+  if (!desc || !out) return fail(MB_EINVAL, "desc and out must not be NULL");
+  *out = nullptr;
+  const mb_plan_desc& d = *desc;
+  if (d.nchans < 1 || d.nchans > 65535) return fail(MB_EINVAL, "nchans %d not in 1..65535", d.nchans);
+  if (d.ndms < 1 || d.ndms > 65535) return fail(MB_EINVAL, "ndms %d not in 1..65535", d.ndms);
+  if (!(d.tsamp_s > 0) || !isfinite(d.tsamp_s)) return fail(MB_EINVAL, "tsamp_s must be > 0");
+  if (!(d.df_mhz != 0) || !isfinite(d.df_mhz)) return fail(MB_EINVAL, "df_mhz must be non-zero");
+  if (!(d.dm_start >= 0) || !(d.dm_step >= 0) || !isfinite(d.dm_start) || !isfinite(d.dm_step))
+    return fail(MB_EINVAL, "dm_start and dm_step must be >= 0");
+  const double flo = d.df_mhz > 0 ? d.f_ch0_mhz : d.f_ch0_mhz + (d.nchans - 1) * d.df_mhz;
+  if (!(flo > 0) || !isfinite(d.f_ch0_mhz)) return fail(MB_EINVAL, "channel centres must be > 0 MHz");
+  if (d.in_dtype != MB_U8 && d.in_dtype != MB_F16 && d.in_dtype != MB_F32)
+    return fail(MB_EINVAL, "in_dtype %d unknown", d.in_dtype);
+  if (d.tile_hint < 0) return fail(MB_EINVAL, "tile_hint must be >= 0");
+  mb_status st = validate_rfi(d.rfi, d.nchans);
+  if (st) return st;
+
+  mb_plan* p = new (std::nothrow) mb_plan;
+  if (!p) return fail(MB_ENOMEM, "host allocation failed");
+  p->desc = d;
+  build_delays(d, p->h_delays, p->smax);
+  // the largest delay must leave room in 32-bit sample arithmetic
+  if ((double)p->smax > 1.0e9) {
+    delete p;
+    return fail(MB_EINVAL, "largest delay %d samples is too large", p->smax);
+  }
+  st = choose_tiling(*p);
+  if (st) { delete p; return st; }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return fail(MB_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)); }
+  const size_t tb = sizeof(int32_t) * p->h_delays.size();
+  p->relb_ld = (d.nchans + 3) & ~3;
+  const size_t rb = sizeof(int32_t) * (size_t)p->relb_ld * d.ndms;
+  if (hipMalloc(&p->d_delays, tb) != hipSuccess || hipMalloc(&p->d_relb, rb) != hipSuccess) {
+    (void)hipFree(p->d_delays);
+    delete p;
+    return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", tb + rb);
+  }
+  e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->relb_ld, p->d_relb, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(p->d_delays);
+    (void)hipFree(p->d_relb);
+    delete p;
+    return fail(MB_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return ok();
+}
+
+mb_status dedisp_plan_destroy(mb_plan* plan) {
+  if (!plan) return ok();
+  (void)hipFree(plan->d_delays);
+  (void)hipFree(plan->d_relb);
+  delete plan;
+  return ok();
+}
+
+mb_status dedisp_plan_info(const mb_plan* plan, mb_plan_info* info) {
+  if (!plan || !info) return fail(MB_EINVAL, "plan and info must not be NULL");
+  info->nchans = plan->desc.nchans;
+  info->ndms = plan->desc.ndms;
+  info->max_delay = plan->smax;
+  info->dm_block = plan->tiling.BD();
+  info->time_tile = plan->tiling.BT();
+  info->chan_block = plan->tiling.BC;
+  info->lds_bytes = (int64_t)plan->lds;
+  return ok();
+}
+
+mb_status dedisp_plan_delays(const mb_plan* plan, int32_t* h_delays) {
+  if (!plan || !h_delays) return fail(MB_EINVAL, "plan and h_delays must not be NULL");
+  memcpy(h_delays, plan->h_delays.data(), sizeof(int32_t) * plan->h_delays.size());
+  return ok();
+}
+
+mb_status rfi_state_layout(const mb_plan* plan, int64_t nsamps, mb_rfi_layout* layout) {
+  if (!plan || !layout) return fail(MB_EINVAL, "plan and layout must not be NULL");
+  if (nsamps < 1 || nsamps > INT32_MAX) return fail(MB_EINVAL, "nsamps must be in 1..2^31-1");
+  const RfiGeom g = rfi_geometry(plan->desc.nchans, nsamps, plan->desc.rfi.window);
+  layout->total_bytes = g.total;
+  layout->fit_f64 = g.off_fit;
+  layout->bandpass_f64 = g.off_binterp;
+  layout->chunk_sum_f64 = g.off_chunk;
+  layout->chunk_flags_u8 = g.off_flags;
+  layout->spectrum_flags_u8 = g.off_gflags;
+  layout->masked_u8 = g.off_masked;
+  layout->nchunks = g.J;
+  return ok();
+}
+
+mb_status rfi_threshold(const mb_plan* plan, const void* d_in, int64_t nsamps, int64_t ld,
+                        void* d_state, size_t state_bytes, void* stream) {
+  mb_status st = validate_input(plan, d_in, nsamps, ld);
+  if (st) return st;
+  const int C = plan->desc.nchans;
+  const mb_rfi_params& r = plan->desc.rfi;
+  if (C < r.poly_order + 2) return fail(MB_EINVAL, "RFI fit needs nchans >= poly_order + 2");
+  if (!d_state || !check_aligned(d_state, 256)) return fail(MB_EINVAL, "state must be non-NULL and 256-byte aligned");
+  const RfiGeom g = rfi_geometry(C, nsamps, r.window);
+  if (state_bytes < g.total) return fail(MB_EINVAL, "state buffer has %zu bytes, needs %zu", state_bytes, g.total);
+  RfiParamsDev prm;
+  prm.p = r.poly_order;
+  prm.W = r.window;
+  prm.mask_passes = r.mask_passes;
+  prm.k_mask = r.k_mask;
+  prm.k_chan = r.k_chan;
+  prm.k_spec = r.k_spec;
+  HIP_TRY(launch_rfi(plan->desc.in_dtype, d_in, ld, g, prm, static_cast<char*>(d_state),
+                     static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_report, void* stream) {
+  if (!plan || !d_state || !h_report) return fail(MB_EINVAL, "plan, state and report must not be NULL");
+  RfiHeader h;
+  HIP_TRY(hipMemcpyAsync(&h, d_state, sizeof(h), hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  h_report->sigma = h.sigma;
+  h_report->rmse0 = h.rmse0;
+  h_report->rmse = h.rmse;
+  h_report->sum_fit = h.sum_fit;
+  h_report->n_masked = (int64_t)h.n_masked;
+  h_report->n_chunk_flags = (int64_t)h.n_chunk;
+  h_report->n_chunk_flags_ext = (int64_t)h.n_chunk_ext;
+  h_report->n_spectrum_flags = (int64_t)h.n_spec;
+  h_report->nsamps = h.nsamps;
+  h_report->nchunks = h.nchunks;
+  h_report->error = h.error;
+  h_report->reserved = 0;
+  return ok();
+}
+
+mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out) {
+  if (!plan || !out) return fail(MB_EINVAL, "plan and out must not be NULL");
+  *out = nullptr;
+  mb_beam* b = new (std::nothrow) mb_beam;
+  if (!b) return fail(MB_ENOMEM, "host allocation failed");
+  b->plan = plan;
+  b->R = ((int64_t)plan->smax + 3) & ~(int64_t)3;
+  if (b->R > 0) {
+    const size_t bytes = sizeof(float) * (size_t)plan->desc.nchans * (size_t)b->R;
+    if (hipMalloc(&b->d_ring, bytes) != hipSuccess) {
+      delete b;
+      return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+  }
+  *out = b;
+  return ok();
+}
+
+mb_status dedisp_beam_destroy(mb_beam* beam) {
+  if (!beam) return ok();
+  (void)hipFree(beam->d_ring);
+  delete beam;
+  return ok();
+}
+
+mb_status dedisp_beam_reset(mb_beam* beam) {
+  if (!beam) return fail(MB_EINVAL, "beam is NULL");
+  beam->seen = 0;
+  return ok();
+}
+
+mb_status dedisp_beam_position(const mb_beam* beam, int64_t* seen) {
+  if (!beam || !seen) return fail(MB_EINVAL, "beam and seen must not be NULL");
+  *seen = beam->seen;
+  return ok();
+}
+
+mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t nsamps,
+                         int64_t ld, const void* d_rfi_state, float* d_out, int64_t ld_out,
+                         mb_norm* d_norm, mb_exec_info* info, void* stream) {
+  mb_status st = validate_input(plan, d_in, nsamps, ld);
+  if (st) return st;
+  if (beam && beam->plan != plan) return fail(MB_EINVAL, "beam was created from another plan");
+  if (d_rfi_state && !check_aligned(d_rfi_state, 256)) return fail(MB_EINVAL, "RFI state must be 256-byte aligned");
+  // Streaming keeps ring length, ring position and chunk starts on
+  // multiples of 4 so that staged quads never straddle the ring/chunk edge.
+  if (beam && nsamps % 4 != 0) return fail(MB_EINVAL, "streaming chunks must hold a multiple of 4 samples");
+  const int64_t smax = plan->smax;
+  const int64_t R = beam ? beam->R : 0;
+  const int64_t seen = beam ? beam->seen : 0;
+  const int64_t v = beam ? (seen < R ? seen : R) : 0;          // ring samples staged
+  const int64_t veff = beam ? (seen < smax ? seen : smax) : 0;  // of which needed
+  const int64_t phase = v - veff;
+  const int64_t nout = veff + nsamps - smax;
+  if (!beam && nout <= 0)
+    return fail(MB_EINVAL, "nsamps (%lld) must exceed the largest delay (%lld)", (long long)nsamps, (long long)smax);
+  const int64_t nout_c = nout > 0 ? nout : 0;
+  if (nout_c > 0) {
+    if (!d_out || !check_aligned(d_out, 16)) return fail(MB_EINVAL, "output must be non-NULL and 16-byte aligned");
+    if (ld_out < nout_c || ld_out % 4 != 0)
+      return fail(MB_EINVAL, "ld_out (%lld) must be >= nout (%lld) and a multiple of 4", (long long)ld_out, (long long)nout_c);
+  }
+  if (d_norm && !check_aligned(d_norm, 8)) return fail(MB_EINVAL, "norm must be 8-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool clean = d_rfi_state != nullptr;
+  CleanView cv{};
+  const float* fit32 = nullptr;
+  if (clean) {
+    const RfiGeom g = rfi_geometry(plan->desc.nchans, nsamps, plan->desc.rfi.window);
+    const char* stp = static_cast<const char*>(d_rfi_state);
+    cv.fit = reinterpret_cast<const double*>(stp + g.off_fit);
+    cv.cflags = reinterpret_cast<const uint8_t*>(stp + g.off_flags);
+    cv.gflags = reinterpret_cast<const uint8_t*>(stp + g.off_gflags);
+    cv.J = g.J;
+    cv.W = (uint32_t)plan->desc.rfi.window;
+    cv.wshift = -1;
+    for (int k = 0; k < 31; ++k)
+      if ((1u << k) == cv.W) cv.wshift = k;
+    fit32 = reinterpret_cast<const float*>(stp + g.off_fit32);
+  }
+  const int64_t sample0 = seen - veff;
+  if (nout_c > 0) {
+    DedispArgs a{};
+    a.x = d_in;
+    a.ld = ld;
+    a.L = nsamps;
+    a.ring = beam ? beam->d_ring : nullptr;
+    a.R = R;
+    a.ring_valid = v;
+    a.ring_p0 = (R > 0) ? (seen - v) % R : 0;
+    a.phase = phase;
+    a.delays = plan->d_delays;
+    a.C = plan->desc.nchans;
+    a.ndms = plan->desc.ndms;
+    a.nout = nout_c;
+    a.out = d_out;
+    a.ld_out = ld_out;
+    a.clean = cv;
+    a.n_dblocks = plan->n_dblocks;
+    a.n_ttiles = (int32_t)((phase + nout_c + plan->tiling.BT() - 1) / plan->tiling.BT());
+    a.rs = plan->rs;
+    a.relb_ld = plan->relb_ld;
+    HIP_TRY(launch_dedisp(plan->desc.in_dtype, clean, beam != nullptr && v > 0, plan->tiling, a, plan->d_relb, fit32,
+                          plan->lds, s));
+  }
+  if (d_norm) {
+    HIP_TRY(launch_norm(d_out, ld_out, nout_c, plan->desc.ndms, reinterpret_cast<NormDev*>(d_norm), s));
+  }
+  if (beam) {
+    if (R > 0)
+      HIP_TRY(launch_ring_update(plan->desc.in_dtype, clean, d_in, ld, nsamps, plan->desc.nchans, cv,
+                                 fit32, beam->d_ring, R, beam->seen, s));
+    beam->seen += nsamps;
+  }
+  if (info) {
+    info->nout = nout_c;
+    info->sample0 = sample0;
+  }
+  return ok();
+}
+
+mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout, int64_t ld_out,
+                           mb_norm* d_norm, void* stream) {
+  if (!plan || !d_norm) return fail(MB_EINVAL, "plan and norm must not be NULL");
+  if (nout < 0) return fail(MB_EINVAL, "nout must be >= 0");
+  if (nout > 0 && (!d_out || !check_aligned(d_out, 16) || ld_out < nout || ld_out % 4 != 0))
+    return fail(MB_EINVAL, "output plane must be 16-byte aligned with ld_out >= nout, ld_out %% 4 == 0");
+  if (!check_aligned(d_norm, 8)) return fail(MB_EINVAL, "norm must be 8-byte aligned");
+  HIP_TRY(launch_norm(d_out, ld_out, nout, plan->desc.ndms, reinterpret_cast<NormDev*>(d_norm),
+                      static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(MB_EINVAL, "plan and bytes must not be NULL");
+  *bytes = detect_work_bytes(plan->desc.ndms);
+  return ok();
+}
+
+mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nout, int64_t ld_out,
+                            const mb_norm* d_norm, int64_t sample0, double nsigma,
+                            mb_candidate* d_cands, int64_t capacity, int64_t* d_count,
+                            mb_peak* d_peaks, void* d_work, size_t work_bytes, void* stream) {
+  if (!plan) return fail(MB_EINVAL, "plan is NULL");
+  if (nout < 0 || sample0 < 0) return fail(MB_EINVAL, "nout and sample0 must be >= 0");
+  if (nout > 0 && (!d_out || !check_aligned(d_out, 16) || ld_out < nout || ld_out % 4 != 0))
+    return fail(MB_EINVAL, "output plane must be 16-byte aligned with ld_out >= nout, ld_out %% 4 == 0");
+  if (!d_norm || !d_count) return fail(MB_EINVAL, "norm and count must not be NULL");
+  if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(MB_EINVAL, "capacity > 0 needs a candidate buffer");
+  if (!isfinite(nsigma)) return fail(MB_EINVAL, "nsigma must be finite");
+  const size_t need = detect_work_bytes(plan->desc.ndms);
+  if (!d_work || work_bytes < need || !check_aligned(d_work, 256))
+    return fail(MB_EINVAL, "workspace must be 256-byte aligned with at least %zu bytes", need);
+  HIP_TRY(launch_detect(d_out, ld_out, nout, plan->desc.ndms, reinterpret_cast<const NormDev*>(d_norm),
+                        sample0, nsigma, plan->desc.dm_start, plan->desc.dm_step,
+                        reinterpret_cast<CandDev*>(d_cands), capacity, d_count,
+                        reinterpret_cast<PeakDev*>(d_peaks), d_work, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,433 @@
+// Thresholding RFI pass of Sec. 2.2.1 on gfx950: bandpass correction,
+// channel (chunk) thresholding and spectrum thresholding.
+//
+// HBM work is one read of the filterbank (rfi_stats_kernel); everything
+// after it touches per-channel, per-chunk or per-sample statistics only,
+// except the spectrum pass, which re-reads the few samples of flagged chunks.
+// All statistics are accumulated in FP64 in a fixed order, so a flag differs
+// from an FP64 reference only for a statistic within rounding of its
+// threshold.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace mbtp {
+namespace {
+
+template <typename T> struct Vec4Load;
+
+template <> struct Vec4Load<float> {
+  static __device__ inline void load(const float* p, double v[4]) {
+    float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  static __device__ inline double one(const float* p) { return (double)*p; }
+};
+template <> struct Vec4Load<__half> {
+  static __device__ inline void load(const __half* p, double v[4]) {
+    uint2 q = *reinterpret_cast<const uint2*>(p);
+    __half2 a = *reinterpret_cast<__half2*>(&q.x), b = *reinterpret_cast<__half2*>(&q.y);
+    float2 fa = __half22float2(a), fb = __half22float2(b);
+    v[0] = fa.x; v[1] = fa.y; v[2] = fb.x; v[3] = fb.y;
+  }
+  static __device__ inline double one(const __half* p) { return (double)__half2float(*p); }
+};
+template <> struct Vec4Load<uint8_t> {
+  static __device__ inline void load(const uint8_t* p, double v[4]) {
+    uint32_t q = *reinterpret_cast<const uint32_t*>(p);
+    v[0] = (double)(q & 0xffu); v[1] = (double)((q >> 8) & 0xffu);
+    v[2] = (double)((q >> 16) & 0xffu); v[3] = (double)(q >> 24);
+  }
+  static __device__ inline double one(const uint8_t* p) { return (double)*p; }
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide FP64 sum over a 1024-thread block; fixed reduction tree.
+__device__ inline double block_sum_1024(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x < 64) {
+    r = (lane < 16) ? sh[lane] : 0.0;
+    r = wave_sum(r);
+    if (lane == 0) sh[16] = r;
+  }
+  __syncthreads();
+  return sh[16];
+}
+
+// ---------------------------------------------------------------------------
+// Statistics pass: one read of x.  Workgroup = (256-sample span, group of CG
+// channels); wave w takes channels g*CG + w, +4, ...; lane l holds samples
+// t0+4l..t0+4l+3.  Writes per-(channel, span) sums and per-(group, sample)
+// partial spectrum sums.
+// ---------------------------------------------------------------------------
+template <typename TIN>
+__global__ __launch_bounds__(256) void rfi_stats_kernel(const TIN* __restrict__ x, int64_t ld,
+                                                        int64_t C, int64_t T, int64_t nspans,
+                                                        int64_t CG, double* __restrict__ span_sum,
+                                                        double* __restrict__ spart) {
+  __shared__ double col_sh[4][kSpan];
+  const int span = blockIdx.x, g = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t0 = (int64_t)span * kSpan;
+  const int64_t tl = t0 + 4 * lane;
+  const int64_t cb = (int64_t)g * CG, ce = min(C, cb + CG);
+  const bool full = (tl + 3 < T);
+  double col[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = cb + wave; c < ce; c += 4) {
+    double v[4];
+    const TIN* row = x + c * ld + tl;
+    if (full) {
+      Vec4Load<TIN>::load(row, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (tl + i < T) ? Vec4Load<TIN>::one(row + i) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) col[i] += v[i];
+    double rs = wave_sum((v[0] + v[1]) + (v[2] + v[3]));
+    if (lane == 0) span_sum[c * nspans + span] = rs;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) col_sh[wave][4 * lane + i] = col[i];
+  __syncthreads();
+  const int64_t t = t0 + threadIdx.x;
+  if (t < T) {
+    const int k = threadIdx.x;
+    spart[(int64_t)g * T + t] = ((col_sh[0][k] + col_sh[1][k]) + col_sh[2][k]) + col_sh[3][k];
+  }
+}
+
+// Per-(channel, chunk) sums from the span sums, and per-channel totals.
+// One wave per channel, lanes over chunks.
+__global__ __launch_bounds__(256) void rfi_chunks_kernel(const double* __restrict__ span_sum,
+                                                         int64_t C, int64_t nspans, int64_t spc,
+                                                         int64_t J, double* __restrict__ chunk_sum,
+                                                         double* __restrict__ bsum) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= C) return;
+  double part = 0.0;
+  for (int64_t j = lane; j < J; j += 64) {
+    double m = 0.0;
+    const int64_t s1 = min(nspans, (j + 1) * spc);
+    for (int64_t s = j * spc; s < s1; ++s) m += span_sum[c * nspans + s];
+    chunk_sum[c * J + j] = m;
+    part += m;
+  }
+  part = wave_sum(part);
+  if (lane == 0) bsum[c] = part;
+}
+
+// ---------------------------------------------------------------------------
+// Bandpass fit on one 1024-thread workgroup.  The least-squares polynomial of
+// degree p over u_c in [-1, 1] is solved through the normal equations in the
+// Legendre basis (well conditioned on equispaced points; same polynomial
+// space, hence the same fit as any other basis up to rounding), by Cholesky.
+// ---------------------------------------------------------------------------
+constexpr int kMaxP = 8;
+
+__device__ inline void legendre(double u, int p, double* P) {
+  P[0] = 1.0;
+  if (p >= 1) P[1] = u;
+  for (int k = 1; k < p; ++k) P[k + 1] = ((2 * k + 1) * u * P[k] - k * P[k - 1]) / (k + 1);
+}
+
+__device__ inline double u_of(int64_t c, int64_t C) {
+  return (2.0 * (double)c - (double)(C - 1)) / (double)(C - 1);
+}
+
+// Fits values v[c] (global), writes the fitted curve to fit[c]; returns RMSE
+// of v - fit.  All threads of the block call it.
+__device__ double fit_poly(const double* v, int64_t C, int p, double* fit, double* sh,
+                           double* coef_sh) {
+  const int n = p + 1;
+  double Gl[(kMaxP + 1) * (kMaxP + 2) / 2];
+  double hl[kMaxP + 1];
+  for (int i = 0; i < (kMaxP + 1) * (kMaxP + 2) / 2; ++i) Gl[i] = 0.0;
+  for (int i = 0; i <= kMaxP; ++i) hl[i] = 0.0;
+  double P[kMaxP + 1];
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    legendre(u_of(c, C), p, P);
+    const double vc = v[c];
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+      hl[i] += P[i] * vc;
+      for (int j = 0; j <= i; ++j) Gl[k++] += P[i] * P[j];
+    }
+  }
+  // reduce the n(n+1)/2 Gram entries and n right-hand sides
+  double G[(kMaxP + 1) * (kMaxP + 2) / 2];
+  double h[kMaxP + 1];
+  const int ng = n * (n + 1) / 2;
+  for (int i = 0; i < ng; ++i) G[i] = block_sum_1024(Gl[i], sh);
+  for (int i = 0; i < n; ++i) h[i] = block_sum_1024(hl[i], sh);
+  if (threadIdx.x == 0) {
+    // Cholesky G = L L^T (packed lower), then two triangular solves
+    double L[(kMaxP + 1) * (kMaxP + 2) / 2];
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j <= i; ++j) {
+        double s = G[i * (i + 1) / 2 + j];
+        for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+        if (i == j) L[i * (i + 1) / 2 + i] = sqrt(s > 0.0 ? s : 0.0);
+        else L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+      }
+    }
+    double y[kMaxP + 1];
+    for (int i = 0; i < n; ++i) {
+      double s = h[i];
+      for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * y[k];
+      y[i] = s / L[i * (i + 1) / 2 + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < n; ++k) s -= L[k * (k + 1) / 2 + i] * coef_sh[k];
+      coef_sh[i] = s / L[i * (i + 1) / 2 + i];
+    }
+  }
+  __syncthreads();
+  double ssq = 0.0;
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    legendre(u_of(c, C), p, P);
+    double f = 0.0;
+    for (int i = 0; i < n; ++i) f += coef_sh[i] * P[i];
+    fit[c] = f;
+    const double r = v[c] - f;
+    ssq += r * r;
+  }
+  const double tot = block_sum_1024(ssq, sh);
+  return sqrt(tot / (double)C);
+}
+
+__global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, RfiParamsDev prm,
+                                                       const double* __restrict__ bsum,
+                                                       double* __restrict__ binterp,
+                                                       double* __restrict__ fit,
+                                                       float* __restrict__ fit32,
+                                                       uint8_t* __restrict__ masked,
+                                                       RfiHeader* __restrict__ hdr) {
+  __shared__ double sh[32];
+  __shared__ double coef_sh[kMaxP + 1];
+  __shared__ int any_left;
+  const double invT = 1.0 / (double)T;
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    binterp[c] = bsum[c] * invT;
+    masked[c] = 0;
+  }
+  __syncthreads();
+  double rmse0 = 0.0;
+  int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
+  for (int pass = 0; pass < passes; ++pass) {
+    const double rmse_i = fit_poly(binterp, C, prm.p, fit, sh, coef_sh);
+    if (pass == 0) rmse0 = rmse_i;
+    const double thr = prm.k_mask * rmse_i;
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+      const double r = bsum[c] * invT - fit[c];
+      if (fabs(r) > thr) masked[c] = 1;
+    }
+    if (threadIdx.x == 0) any_left = 0;
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+      if (!masked[c]) atomicOr(&any_left, 1);
+    }
+    __syncthreads();
+    if (!any_left) break;
+    // nearest unmasked neighbour on each side (one side at a band edge)
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+      if (!masked[c]) { binterp[c] = bsum[c] * invT; continue; }
+      int64_t l = c - 1, r = c + 1;
+      while (l >= 0 && masked[l]) --l;
+      while (r < C && masked[r]) ++r;
+      double v;
+      if (l >= 0 && r < C) v = (bsum[l] * invT + bsum[r] * invT) * 0.5;
+      else if (l >= 0) v = bsum[l] * invT;
+      else v = bsum[r] * invT;
+      binterp[c] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    hdr->nsamps = T;
+    hdr->nchunks = (T + prm.W - 1) / prm.W;
+  }
+  if (!any_left) {
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) fit32[c] = 0.0f;
+    if (threadIdx.x == 0) {
+      hdr->error = 1; hdr->sigma = 0.0; hdr->rmse0 = rmse0; hdr->rmse = 0.0;
+      hdr->sum_fit = 0.0; hdr->thr_spec = 0.0; hdr->k_chan = prm.k_chan;
+      hdr->n_masked = (unsigned long long)C; hdr->n_chunk = hdr->n_chunk_ext = hdr->n_spec = 0;
+    }
+    return;
+  }
+  const double rmse = fit_poly(binterp, C, prm.p, fit, sh, coef_sh);
+  double sf = 0.0, nm = 0.0;
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    fit32[c] = (float)fit[c];
+    sf += fit[c];
+    nm += masked[c] ? 1.0 : 0.0;
+  }
+  sf = block_sum_1024(sf, sh);
+  nm = block_sum_1024(nm, sh);
+  if (threadIdx.x == 0) {
+    const double sigma = rmse * sqrt((double)T * (double)C / (double)(C - prm.p - 1));
+    hdr->sigma = sigma;
+    hdr->rmse0 = rmse0;
+    hdr->rmse = rmse;
+    hdr->sum_fit = sf;
+    hdr->thr_spec = prm.k_spec * sigma / sqrt((double)C);
+    hdr->k_chan = prm.k_chan;
+    hdr->n_masked = (unsigned long long)nm;
+    hdr->n_chunk = hdr->n_chunk_ext = hdr->n_spec = 0;
+    hdr->error = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chunk flags: one workgroup per chunk j, threads over channels.  F[c][j] is
+// |M[c][j]/L_j - f_c| > k_chan*sigma/sqrt(L_j); the extended flag also takes
+// the time-adjacent chunks j-1 and j+1 of the same channel.  The flagged
+// channels of chunk j are listed in ascending order for the spectrum pass.
+// ---------------------------------------------------------------------------
+__device__ inline bool chunk_over(const double* M, const double* fit, int64_t c, int64_t j,
+                                  int64_t J, int64_t T, int64_t W, double sigma, double k) {
+  const int64_t L = min(W, T - j * W);
+  const double m = M[c * J + j] / (double)L - fit[c];
+  return fabs(m) > k * sigma / sqrt((double)L);
+}
+
+__global__ __launch_bounds__(256) void rfi_chunk_flags_kernel(const double* __restrict__ M,
+                                                              const double* __restrict__ fit,
+                                                              int64_t C, int64_t T, int64_t W,
+                                                              int64_t J, RfiHeader* __restrict__ hdr,
+                                                              uint8_t* __restrict__ flags,
+                                                              int32_t* __restrict__ lcount,
+                                                              int32_t* __restrict__ list) {
+  __shared__ int wcount[4];
+  const int64_t j = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool err = hdr->error != 0;
+  const double sigma = hdr->sigma, k = hdr->k_chan;
+  int64_t base = 0;
+  int n0 = 0, n1 = 0;
+  for (int64_t c0 = 0; c0 < C; c0 += 256) {
+    const int64_t c = c0 + threadIdx.x;
+    bool f0 = false, fx = false;
+    if (c < C && !err) {
+      f0 = chunk_over(M, fit, c, j, J, T, W, sigma, k);
+      const bool fm = (j > 0) && chunk_over(M, fit, c, j - 1, J, T, W, sigma, k);
+      const bool fp = (j + 1 < J) && chunk_over(M, fit, c, j + 1, J, T, W, sigma, k);
+      fx = f0 || fm || fp;
+    }
+    if (c < C) flags[c * J + j] = (uint8_t)((f0 ? 1 : 0) | (fx ? 2 : 0));
+    n0 += f0; n1 += fx;
+    const unsigned long long bal = __ballot(fx);
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wcount[w];
+    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (fx) {
+      const unsigned long long lower = (lane == 0) ? 0ull : (bal & ((1ull << lane) - 1ull));
+      list[j * C + base + before + __popcll(lower)] = (int32_t)c;
+    }
+    base += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lcount[j] = (int32_t)base;
+  // counts (integer atomics: order-free)
+  int a0 = n0, a1 = n1;
+  for (int off = 32; off >= 1; off >>= 1) {
+    a0 += __shfl_xor(a0, off, 64);
+    a1 += __shfl_xor(a1, off, 64);
+  }
+  if (lane == 0 && (a0 | a1)) {
+    atomicAdd(&hdr->n_chunk, (unsigned long long)a0);
+    atomicAdd(&hdr->n_chunk_ext, (unsigned long long)a1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum flags: s[t] = (sum_c (x - f_c) - sum over flagged chunks' (x - f_c)) / C,
+// G[t] = |s[t]| > k_spec*sigma/sqrt(C).  One thread per sample.
+// ---------------------------------------------------------------------------
+template <typename TIN>
+__global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
+    const TIN* __restrict__ x, int64_t ld, int64_t C, int64_t T, int64_t W, int64_t J,
+    const double* __restrict__ spart, int64_t ngroups, const double* __restrict__ fit,
+    const int32_t* __restrict__ lcount, const int32_t* __restrict__ list,
+    RfiHeader* __restrict__ hdr, uint8_t* __restrict__ gflags) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  bool g = false;
+  if (t < T && hdr->error == 0) {
+    double S = 0.0;
+    for (int64_t k = 0; k < ngroups; ++k) S += spart[k * T + t];
+    const int64_t j = t / W;
+    double corr = 0.0;
+    const int n = lcount[j];
+    for (int k = 0; k < n; ++k) {
+      const int64_t c = list[j * C + k];
+      corr += Vec4Load<TIN>::one(x + c * ld + t) - fit[c];
+    }
+    const double s = ((S - hdr->sum_fit) - corr) / (double)C;
+    g = fabs(s) > hdr->thr_spec;
+  }
+  if (t < T) gflags[t] = g ? 1 : 0;
+  unsigned long long cnt = __popcll(__ballot(g));
+  if (lane == 0 && cnt) atomicAdd(&hdr->n_spec, cnt);
+}
+
+template <typename TIN>
+hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiParamsDev& prm,
+                        char* st, hipStream_t s) {
+  double* span_sum = reinterpret_cast<double*>(st + g.off_span);
+  double* spart = reinterpret_cast<double*>(st + g.off_spart);
+  double* chunk = reinterpret_cast<double*>(st + g.off_chunk);
+  double* bsum = reinterpret_cast<double*>(st + g.off_bsum);
+  double* binterp = reinterpret_cast<double*>(st + g.off_binterp);
+  double* fit = reinterpret_cast<double*>(st + g.off_fit);
+  float* fit32 = reinterpret_cast<float*>(st + g.off_fit32);
+  uint8_t* masked = reinterpret_cast<uint8_t*>(st + g.off_masked);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(st + g.off_flags);
+  uint8_t* gflags = reinterpret_cast<uint8_t*>(st + g.off_gflags);
+  int32_t* lcount = reinterpret_cast<int32_t*>(st + g.off_lcount);
+  int32_t* list = reinterpret_cast<int32_t*>(st + g.off_list);
+  RfiHeader* hdr = reinterpret_cast<RfiHeader*>(st + g.off_hdr);
+
+  hipLaunchKernelGGL(rfi_stats_kernel<TIN>, dim3((unsigned)g.nspans, (unsigned)g.ngroups),
+                     dim3(256), 0, s, x, ld, g.C, g.T, g.nspans, g.CG, span_sum, spart);
+  hipLaunchKernelGGL(rfi_chunks_kernel, dim3((unsigned)((g.C + 3) / 4)), dim3(256), 0, s,
+                     span_sum, g.C, g.nspans, g.W / kSpan, g.J, chunk, bsum);
+  hipLaunchKernelGGL(rfi_fit_kernel, dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, binterp,
+                     fit, fit32, masked, hdr);
+  hipLaunchKernelGGL(rfi_chunk_flags_kernel, dim3((unsigned)g.J), dim3(256), 0, s, chunk, fit,
+                     g.C, g.T, g.W, g.J, hdr, flags, lcount, list);
+  hipLaunchKernelGGL(rfi_spectrum_flags_kernel<TIN>, dim3((unsigned)((g.T + 255) / 256)),
+                     dim3(256), 0, s, x, ld, g.C, g.T, g.W, g.J, spart, g.ngroups, fit, lcount,
+                     list, hdr, gflags);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rfi(int dtype, const void* x, int64_t ld, const RfiGeom& g,
+                      const RfiParamsDev& prm, char* state, hipStream_t s) {
+  switch (dtype) {
+    case 0: return launch_rfi_t(static_cast<const uint8_t*>(x), ld, g, prm, state, s);
+    case 1: return launch_rfi_t(static_cast<const __half*>(x), ld, g, prm, state, s);
+    default: return launch_rfi_t(static_cast<const float*>(x), ld, g, prm, state, s);
+  }
+}
+
+}  // namespace mbtp

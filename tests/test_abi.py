@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/mbtp.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mbtp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def _lib():
+    from paper_1307_5700_amd import _lib as L
+    return L
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("dedisp_plan_create", "dedisp_execute", "rfi_threshold", "detect_candidates"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = L.lib()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(_declared()) <= exported
+    # the binding's prototypes cover the same set
+    assert set(L.exported_symbols()) == set(_declared())
+
+
+def test_links_hip_runtime_by_soname():
+    L = _lib()
+    out = subprocess.run(["readelf", "-d", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "libamdhip64.so.7" in out
+
+
+def test_status_strings_and_defaults():
+    L = _lib()
+    lib = L.lib()
+    assert lib.mb_status_str(L.MB_EINVAL) == b"invalid argument"
+    p = L.RfiParams()
+    lib.mb_rfi_defaults(ctypes.byref(p))
+    assert (p.poly_order, p.window, p.k_mask, p.k_chan, p.k_spec, p.mask_passes) == (3, 256, 5.0, 5.0, 5.0, 1)
+
+
+def _desc(L, **kw):
+    r = L.RfiParams()
+    L.lib().mb_rfi_defaults(ctypes.byref(r))
+    d = dict(nchans=256, ndms=64, f_ch0_mhz=398.0390625, df_mhz=0.078125, tsamp_s=1e-4,
+             dm_start=0.0, dm_step=1.0, in_dtype=L.MB_F32, tile_hint=0)
+    d.update(kw)
+    return L.PlanDesc(d["nchans"], d["ndms"], d["f_ch0_mhz"], d["df_mhz"], d["tsamp_s"], d["dm_start"],
+                      d["dm_step"], d["in_dtype"], d["tile_hint"], r)
+
+
+@pytest.mark.parametrize("bad", [dict(nchans=0), dict(ndms=0), dict(tsamp_s=0.0), dict(df_mhz=0.0),
+                                 dict(dm_step=-1.0), dict(in_dtype=7), dict(f_ch0_mhz=-5.0),
+                                 dict(tile_hint=-1)])
+def test_plan_create_rejects_bad_descriptors(bad):
+    L = _lib()
+    d = _desc(L, **bad)
+    h = ctypes.c_void_p()
+    st = L.lib().dedisp_plan_create(ctypes.byref(d), ctypes.byref(h))
+    assert st == L.MB_EINVAL
+    assert h.value is None
+    assert L.lib().mb_last_error()
+
+
+def test_bad_rfi_params_rejected():
+    L = _lib()
+    d = _desc(L)
+    d.rfi.window = 100                    # not a multiple of 256
+    h = ctypes.c_void_p()
+    assert L.lib().dedisp_plan_create(ctypes.byref(d), ctypes.byref(h)) == L.MB_EINVAL
+    assert b"window" in L.lib().mb_last_error()
+
+
+def test_null_plan_calls_rejected():
+    L = _lib()
+    lib = L.lib()
+    assert lib.dedisp_execute(None, None, None, 10, 12, None, None, 12, None, None, None) == L.MB_EINVAL
+    assert lib.rfi_threshold(None, None, 10, 12, None, 0, None) == L.MB_EINVAL
+    assert lib.detect_candidates(None, None, 0, 0, None, 0, 6.0, None, 0, None, None, None, 0, None) == L.MB_EINVAL
+    assert lib.dedisp_plan_destroy(None) == L.MB_OK

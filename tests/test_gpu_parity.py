@@ -1,0 +1,249 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Bars: delay tables, RFI flags and candidate (DM, sample) sets bit-exact;
+every dedispersed sample within 1e-5 relative (to its own magnitude, floored
+at its series' noise std; FP32 arithmetic); normalisation lines within the
+same relative scale.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1307_5700_amd import synth
+
+from gpu_util import (api, beam_input, compare_candidates, err_noise, err_sigma, oracle_plan,
+                      rfi_params, run_gpu, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _peaks_match(gp, z_or, tol=1e-4):
+    op = z_or.argmax(axis=1)
+    for d in range(z_or.shape[0]):
+        row = z_or[d]
+        top = row[op[d]]
+        assert abs(float(gp["snr"][d]) - top) < tol, d
+        second = np.partition(row, -2)[-2] if row.size > 1 else -np.inf
+        if top - second > tol:
+            assert gp["sample"][d] == op[d], d
+
+
+@pytest.mark.parametrize("beam", [synth.plain_single_beam(), synth.paper_beam(), synth.precision_beam(),
+                                  synth.tiny_beam(nchans=16, ndms=9, dm_step=3.0)],
+                         ids=["plain256", "paper1024", "precision4096", "tiny16"])
+def test_delay_table_bit_exact(beam):
+    A = api()
+    plan = A.Plan.from_beam(beam)
+    ref = oracle.delay_table(**beam.plan_kwargs())
+    assert np.array_equal(plan.delays(), ref)
+    assert plan.max_delay == ref.max()
+
+
+def test_delay_table_descending_band_and_offset_start():
+    A = api()
+    b = synth.paper_beam()
+    p = b.plan_kwargs()
+    fhi = p["f_ch0_mhz"] + (p["nchans"] - 1) * p["df_mhz"]
+    for kw in ({**p, "f_ch0_mhz": fhi, "df_mhz": -p["df_mhz"]}, {**p, "dm_start": 12.5, "dm_step": 0.25}):
+        plan = A.Plan(**kw)
+        assert np.array_equal(plan.delays(), oracle.delay_table(**kw))
+
+
+def test_plain_beam_no_rfi():
+    A = api()
+    beam = synth.plain_single_beam()
+    x, s = beam_input(beam)
+    plan = A.Plan.from_beam(beam)
+    g = run_gpu(plan, to_dev(x), rfi=False, nsigma=beam.nsigma)
+    r = oracle.run(x, oracle_plan(beam), None, beam.nsigma)
+    assert g["nout"] == r["nout"] == 8192 - 1536
+    assert err_sigma(g["D"], r["D"]) < TOL
+    nr = r["norm"]
+    sd = r["D"].std(axis=1)
+    np.testing.assert_allclose(g["norm"]["a"], nr.a, rtol=0, atol=1e-5 * sd.max())
+    np.testing.assert_allclose(g["norm"]["b"] * g["nout"], nr.b * g["nout"], rtol=0, atol=1e-5 * sd.max())
+    np.testing.assert_allclose(g["norm"]["sigma"], nr.sigma, rtol=1e-6)
+    assert not g["norm"]["degenerate"].any()
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+    _peaks_match(g["peaks"], nr.z)
+    p = beam.pulses[0]
+    assert p.t0 <= g["peaks"]["sample"][p.dm_index] < p.t0 + p.width
+
+
+def _check_rfi(g, r):
+    o = r["rfi"]
+    a = g["rfi"]
+    assert np.array_equal(a["masked"], o.masked)
+    assert np.array_equal(a["chunk_flags"], o.chunk_flags)
+    assert np.array_equal(a["chunk_flags_ext"], o.chunk_flags_ext)
+    assert np.array_equal(a["spectrum_flags"], o.spectrum_flags)
+    np.testing.assert_allclose(a["fit"], o.fit, rtol=0, atol=1e-9 * max(1.0, np.abs(o.fit).max()))
+    rep = g["report"]
+    assert rep["sigma"] == pytest.approx(o.sigma, rel=1e-9)
+    assert rep["rmse0"] == pytest.approx(o.rmse0, rel=1e-9)
+    assert rep["n_masked"] == o.masked.sum()
+    assert rep["n_chunk_flags"] == o.chunk_flags.sum()
+    assert rep["n_chunk_flags_ext"] == o.chunk_flags_ext.sum()
+    assert rep["n_spectrum_flags"] == o.spectrum_flags.sum()
+    assert rep["error"] == 0
+    t = o.near_ties
+    assert t.get("chunk_count", 0) == 0 and t.get("spectrum_count", 0) == 0 and t.get("mask_count", 0) == 0
+
+
+def test_plain_beam_with_rfi_and_injected_rfi():
+    A = api()
+    beam = synth.plain_single_beam(rfi=True)
+    beam.bursts = [synth.Burst(c0=100, nch=5, t0=3000, length=1500, amp=20.0)]
+    beam.spikes = [synth.Spike(t0=5000, length=1, amp=20.0)]
+    x, s = beam_input(beam)
+    plan = A.Plan.from_beam(beam)
+    g = run_gpu(plan, to_dev(x), rfi=True, nsigma=beam.nsigma)
+    r = oracle.run(x, oracle_plan(beam), rfi_params(plan.rfi_config), beam.nsigma)
+    _check_rfi(g, r)
+    assert r["rfi"].spectrum_flags[5000] and r["rfi"].chunk_flags[100:105].any()
+    assert err_sigma(g["D"], r["D"]) < TOL
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+
+
+def test_paper_beam_full_plane():
+    """1024 channels, 65536 samples, 640 DMs, RFI at 20 sigma, 5 sigma
+    thresholds: every flag, every dedispersed sample and every candidate."""
+    A = api()
+    beam = synth.paper_beam()
+    x, s = beam_input(beam)
+    plan = A.Plan.from_beam(beam)
+    g = run_gpu(plan, to_dev(x), rfi=True, nsigma=beam.nsigma)
+    r = oracle.run(x, oracle_plan(beam), rfi_params(plan.rfi_config), beam.nsigma)
+    _check_rfi(g, r)
+    assert g["nout"] == 65536 - 6102
+    assert err_sigma(g["D"], r["D"]) < TOL
+    assert err_noise(g["D"], r["D"]) < TOL
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+    _peaks_match(g["peaks"], r["norm"].z)
+    for p in beam.pulses:
+        if p.amp * 32 > 8:
+            assert p.t0 - 2 <= g["peaks"]["sample"][p.dm_index] < p.t0 + p.width + 2
+
+
+def test_tiling_does_not_change_a_bit():
+    A = api()
+    beam = synth.paper_beam(nsamps=16384)
+    beam.ndms = 200
+    beam.pulses = [p for p in beam.pulses if p.dm_index < 200]
+    x, _ = beam_input(beam)
+    xd = to_dev(x)
+    ref = None
+    used = set()
+    for hint in range(1, 7):
+        try:
+            plan = A.Plan.from_beam(beam, tile_hint=hint)
+        except A.L.MbError:
+            continue
+        used.add((plan.tiling["dm_block"], plan.tiling["time_tile"], plan.tiling["chan_block"]))
+        st = plan.rfi_threshold(xd)
+        out, norm, nout, _ = plan.execute(xd, rfi_state=st)
+        D = out[:, :nout].cpu().numpy()
+        if ref is None:
+            ref = D
+        else:
+            assert np.array_equal(D, ref), hint
+    assert len(used) >= 4
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
+def test_storage_types_ragged_shapes(dtype):
+    """Odd channel/DM counts, a ragged last chunk and window, p = 2."""
+    A = api()
+    f0, df = synth.band(300)
+    beam = synth.Beam(name="ragged", nchans=300, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6, ndms=37,
+                      dm_start=1.3, dm_step=0.7, nsamps=9001, dtype=dtype, seed=41,
+                      bursts=[synth.Burst(c0=17, nch=3, t0=2000, length=1100, amp=20.0)],
+                      spikes=[synth.Spike(t0=7001, length=2, amp=20.0)])
+    s = oracle.delay_table(**beam.plan_kwargs())
+    beam.pulses = [synth.Pulse(dm_index=30, t0=1000, width=5, amp=1.0)]
+    x = synth.render(beam, s)
+    cfg = A.RfiConfig(poly_order=2, window=512)
+    plan = A.Plan.from_beam(beam, rfi=cfg)
+    g = run_gpu(plan, to_dev(x, ld=9004), rfi=True, nsigma=6.0)
+    r = oracle.run(x, oracle_plan(beam), rfi_params(cfg), 6.0)
+    _check_rfi(g, r)
+    assert err_sigma(g["D"], r["D"]) < TOL
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+    # without RFI cleaning u8 sums are integers below 2^24: bitwise exact
+    if dtype == "u8":
+        g2 = run_gpu(plan, to_dev(x, ld=9004), rfi=False, nsigma=6.0)
+        r2 = oracle.run(x, oracle_plan(beam), None, 6.0)
+        assert np.array_equal(g2["D"].astype(np.float64), r2["D"])
+
+
+def test_normalise_and_detect_on_a_given_plane():
+    """Normalisation + detection fed the same FP32 plane on both sides."""
+    A = api()
+    rng = np.random.default_rng(77)
+    beam = synth.tiny_beam(nchans=8, ndms=50, dm_step=0.0)
+    plan = A.Plan.from_beam(beam)
+    N = 10001
+    D = (rng.standard_normal((50, N)) * 5 + 3.0 + 1e-3 * np.arange(N)[None, :]).astype(np.float32)
+    D[7, 5000] += 60.0
+    D[7, 5001] += 60.0
+    D[20] = np.float32(2.0) * np.arange(N, dtype=np.float32)      # exactly linear: degenerate
+    D[21] = 4.0                                                      # constant: degenerate
+    out = torch.zeros((50, N + 3), dtype=torch.float32, device="cuda")
+    out[:, :N] = torch.from_numpy(D).cuda()
+    norm = plan.normalise(out, N)
+    bufs = plan.detect(out, N, norm, 5.0, sample0=123, capacity=1 << 14)
+    torch.cuda.synchronize()
+    gn = plan.norm_to_host(norm)
+    nr = oracle.normalise(D.astype(np.float64))
+    assert np.array_equal(gn["degenerate"].astype(bool), nr.degenerate)
+    assert nr.degenerate[20] and nr.degenerate[21] and nr.degenerate.sum() == 2
+    ok = ~nr.degenerate
+    np.testing.assert_allclose(gn["sigma"][ok], nr.sigma[ok], rtol=1e-12)
+    np.testing.assert_allclose(gn["b"][ok] * N, nr.b[ok] * N, rtol=0, atol=1e-12 * nr.sigma[ok].max())
+    np.testing.assert_allclose(gn["a"][ok], nr.a[ok], rtol=0, atol=1e-12 * nr.sigma[ok].max())
+    gc, n = plan.candidates_to_host(bufs[0], bufs[1])
+    oc, op, margin = oracle.detect(nr.z, 5.0, 123, oracle.dm_trials(50, 0.0, 0.0))
+    assert margin > 1e-9
+    assert n == len(oc)
+    assert np.array_equal(gc["dm_index"], oc["dm_index"]) and np.array_equal(gc["sample"], oc["sample"])
+    np.testing.assert_allclose(gc["snr"], oc["snr"], rtol=1e-6)
+    gp = plan.peaks_to_host(bufs[2])
+    np.testing.assert_array_equal(gp["sample"], op["sample"])
+    np.testing.assert_allclose(gp["snr"], op["snr"], rtol=1e-6)
+    assert gp["snr"][20] == 0 and gp["sample"][20] == 123
+
+
+def test_capacity_overflow_reports_true_count():
+    A = api()
+    beam = synth.plain_single_beam()
+    x, _ = beam_input(beam)
+    plan = A.Plan.from_beam(beam)
+    xd = to_dev(x)
+    out, norm, nout, _ = plan.execute(xd)
+    full = plan.detect(out, nout, norm, 2.0, capacity=1 << 20)
+    small = plan.detect(out, nout, norm, 2.0, capacity=10)
+    torch.cuda.synchronize()
+    c_full, n_full = plan.candidates_to_host(full[0], full[1])
+    c_small, n_small = plan.candidates_to_host(small[0], small[1])
+    assert n_full == n_small > 10
+    assert len(c_small) == 10
+    assert np.array_equal(c_small, c_full[:10])
+
+
+def test_invalid_calls_enqueue_nothing():
+    A = api()
+    beam = synth.plain_single_beam()
+    plan = A.Plan.from_beam(beam)
+    short = torch.zeros((256, 1536), dtype=torch.float32, device="cuda")
+    with pytest.raises(A.L.MbError) as e:
+        plan.execute(short)
+    assert e.value.status == A.L.MB_EINVAL
+    base = torch.zeros((256, 4100), dtype=torch.float32, device="cuda")
+    with pytest.raises(A.L.MbError):
+        plan.execute(base[:, 1:])          # misaligned rows
+    wrong = torch.zeros((256, 4096), dtype=torch.float16, device="cuda")
+    with pytest.raises(ValueError):
+        plan.execute(wrong)

@@ -148,3 +148,25 @@ def test_empty_and_short_inputs():
     assert oracle.dedisperse(y, s).shape == (5, 0)
     with pytest.raises(ValueError):
         oracle.dedisperse(np.zeros((8, int(s.max()) - 1)), s)
+
+
+def test_stream_outputs_tile_the_single_shot_plane():
+    """Without cleaning, the blocks emitted after each chunk are consecutive
+    slices of the single-shot plane; a single chunk gives the whole plane."""
+    rng = np.random.default_rng(16)
+    s = _tiny_delays(C=16, nd=10, step=3.0)
+    smax = int(s.max())
+    x = rng.standard_normal((16, 500)).astype(np.float32)
+    whole = oracle.dedisperse(x, s)
+    cuts = [smax // 2, 3, smax, 200, 500 - smax // 2 - 3 - smax - 200]
+    chunks, a = [], 0
+    for L_ in cuts:
+        chunks.append(x[:, a:a + L_])
+        a += L_
+    blocks = oracle.stream_outputs(chunks, s, None)
+    assert blocks[0][1].shape[1] == 0
+    cat = np.concatenate([b for _, b in blocks], axis=1)
+    assert np.array_equal(cat, whole)
+    assert [b0 for b0, _ in blocks] == sorted(b0 for b0, _ in blocks)
+    one = oracle.stream_outputs([x], s, oracle.RfiParams())
+    assert np.array_equal(one[0][1], oracle.dedisperse(oracle.rfi_clean(x, oracle.RfiParams()).y, s))
