@@ -36,39 +36,79 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=64,
-                    help="DM rows of the CPU-baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU work of the oracle baseline sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy 256 MiB device-to-device once (a kernel of "
+                         "known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
+                         "WRITE_SIZE) into profiles/dedisp_traffic.txt and exit")
     return ap.parse_args()
 
 
-def cpu_baseline(beam, x, nrows: int):
-    """The oracle, as it is, on a bounded sample of the same workload: the
-    full RFI pass of the chunk plus dedispersion, normalisation and
-    detection of `nrows` evenly spaced DM rows; extrapolated linearly in the
-    number of DMs to a per-step time."""
+CALIB_BYTES = 256 * 1024 * 1024
+
+
+def traffic_summary(fetch_csv: str, write_csv: str) -> None:
+    """HBM bytes per dedispersion launch from the PMC runs, each counter
+    scaled by what it reads for the calibration copy of known size."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "dedisp" if "dedisp_kernel" in name else ("copy" if "copyBuffer" in name else None)
+            if key:
+                vals.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+        return vals
+
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale = CALIB_BYTES / float(np.mean(f["copy"]))
+    w_scale = CALIB_BYTES / float(np.mean(w["copy"]))
+    fetch = float(np.mean(f["dedisp"])) * f_scale
+    write = float(np.mean(w["dedisp"])) * w_scale
+    path = os.path.join(ROOT, "profiles", "dedisp_traffic.txt")
+    with open(path, "w") as fh:
+        fh.write("# HBM traffic of one dedisp_kernel launch, bench workload "
+                 "(1024 ch x 65536 samples x 640 DMs, f32, RFI on)\n")
+        fh.write("# from: rocprofv3 --pmc FETCH_SIZE ... and --pmc WRITE_SIZE ... -- python3 bench.py "
+                 "--steps 3 --warmup 1 --no-cpu-baseline --calib-copy\n")
+        fh.write(f"kernel_source_hash={_kernel_hash()}\n")
+        fh.write(f"fetch_scale={f_scale:.4f}\nwrite_scale={w_scale:.4f}\n")
+        fh.write(f"fetch_bytes={fetch:.0f}\nwrite_bytes={write:.0f}\n")
+        fh.write(f"bytes_per_launch={fetch + write:.0f}\n")
+    print(open(path).read())
+
+
+def cpu_baseline(beam, x, min_seconds: float = 10.0, max_reps: int = 8):
+    """The oracle, as it is, on the same workload: the whole step (FP64 RFI
+    pass, dedispersion of every DM, normalisation, detection) repeated until
+    about `min_seconds` of CPU work has been done."""
     import oracle
     plan = oracle.PlanDesc(**beam.plan_kwargs())
-    s = oracle.delay_table(**beam.plan_kwargs())
-    nout = x.shape[1] - int(s.max())
-    rows = np.linspace(0, beam.ndms - 1, nrows).round().astype(np.int32)
-    t0 = time.perf_counter()
-    r = oracle.rfi_clean(x, oracle.RfiParams())
-    t1 = time.perf_counter()
-    D = oracle.dedisperse_rows(r.y, s, rows, nout)
-    nr = oracle.normalise(D)
-    oracle.detect(nr.z, beam.nsigma)
-    t2 = time.perf_counter()
-    t_step = (t1 - t0) + (t2 - t1) * beam.ndms / nrows
-    del plan
-    return {"value": beam.ndms * nout / t_step, "unit": "DM-trial samples/s",
+    reps, t_total, nout = 0, 0.0, 0
+    while reps < max_reps and (t_total < min_seconds or reps == 0):
+        t0 = time.perf_counter()
+        r = oracle.run(x, plan, oracle.RfiParams(), beam.nsigma)
+        t_total += time.perf_counter() - t0
+        nout = r["nout"]
+        reps += 1
+    return {"value": beam.ndms * nout * reps / t_total, "unit": "DM-trial samples/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": (f"full FP64 RFI pass ({t1 - t0:.2f} s) + {nrows} of {beam.ndms} DM rows "
-                       f"dedispersed/normalised/thresholded ({t2 - t1:.2f} s), "
-                       f"time per step extrapolated linearly in DMs: {t_step:.2f} s")}
+            "sample": (f"{reps} full steps of the same chunk ({beam.ndms} DMs x {nout} outputs, "
+                       f"FP64 RFI pass + dedispersion + normalisation + detection) in {t_total:.1f} s")}
 
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_summary(*args.traffic_from)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the design notes describe how it would shard by beam, DM or time)", file=sys.stderr)
@@ -121,12 +161,21 @@ def main():
     k_ms = stage["dedisp"]
     achieved = adds / (k_ms * 1e-3) / 1e12
 
+    if args.calib_copy:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # HBM bytes per launch from the committed PMC summary, if it was taken on
+    # this kernel source (null otherwise)
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "dedisp_traffic.json")
+    tf = os.path.join(ROOT, "profiles", "dedisp_traffic.txt")
     if os.path.exists(tf):
-        tj = json.load(open(tf))
-        if tj.get("kernel_source_hash") == _kernel_hash():
-            traffic = tj.get("bytes_per_launch")
+        kv = dict(l.strip().split("=", 1) for l in open(tf) if "=" in l and not l.startswith("#"))
+        if kv.get("kernel_source_hash") == _kernel_hash():
+            traffic = float(kv["bytes_per_launch"])
 
     res = {
         "metric": "DM-trial samples/s",
@@ -154,7 +203,7 @@ def main():
         "rfi_pass_hbm_gbs": (x.numel() * 4) / (stage["rfi"] * 1e-3) / 1e9,
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(beam, x_host, args.cpu_rows)
+        res["cpu_baseline"] = cpu_baseline(beam, x_host, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -59,7 +59,7 @@ enum { MB_U8 = 0, MB_F16 = 1, MB_F32 = 2 };
  * brackets; mb_rfi_defaults() fills them. */
 typedef struct {
   int32_t poly_order;   /* p of the bandpass polynomial, 0..8 [3]           */
-  int32_t window;       /* W_c, chunk width in samples, multiple of 256 [256] */
+  int32_t window;       /* W_c, chunk width in samples, power of 2 >= 256 [256] */
   double k_mask;        /* channel masking factor x RMSE of the fit [5]      */
   double k_chan;        /* chunk-mean threshold in noise stds [5]            */
   double k_spec;        /* spectrum-mean threshold in noise stds [5]         */
@@ -229,15 +229,55 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in,
 mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout,
                            int64_t ld_out, mb_norm* d_norm, void* stream);
 
+/* ---- batched launch ------------------------------------------------------ */
+
+/* One beam chunk of a batch: the arguments of one dedisp_execute call. */
+typedef struct {
+  const mb_plan* plan;
+  mb_beam* beam;               /* NULL: single shot; a beam appears at most once */
+  const void* d_in;
+  int64_t nsamps, ld;
+  const void* d_rfi_state;     /* either every item of a batch has one, or none */
+  float* d_out;
+  int64_t ld_out;
+  mb_norm* d_norm;             /* nullable */
+} mb_batch_item;
+
+/* Bytes of caller-owned device workspace for a batch of nitems (a tile
+ * counter per launch of up to 16 items). */
+mb_status dedisp_batch_workspace_size(int32_t nitems, size_t* bytes);
+
+/* Dedisperses many beams' chunks (Sec. 2, multibeam: beams are independent)
+ * in one persistent launch per 16 items: workgroups take (item, DM block,
+ * time tile) work from an atomic counter, heaviest channel counts first, so
+ * beams with uneven channel counts, DM plans and chunk lengths share the GPU.
+ * Every item gives exactly the result dedisp_execute gives it alone (same
+ * summation order), including streaming beams.  All plans must share the
+ * storage type and the tiling (plan_info dm_block/time_tile/chan_block, set
+ * through tile_hint).  infos (nullable, host, [nitems]) receives each item's
+ * nout and sample0.  d_work: dedisp_batch_workspace_size bytes, 256-byte
+ * aligned.  Arguments of every item are validated before anything is
+ * enqueued.  Errors: MB_EINVAL. */
+mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void* d_work,
+                               size_t work_bytes, mb_exec_info* infos, void* stream);
+
 /* ---- streaming state --------------------------------------------------- */
 
 /* A beam's device-resident overlap ring: the last R cleaned FP32 samples of
  * every channel, R = s_max rounded up to a multiple of 4, plus the absolute
- * sample count.  Allocates nchans * R * 4 bytes on the plan's device. */
+ * sample count, kept both on the host and on the device (the kernels read the
+ * ring position from the device copy, so a captured steady-state chunk step,
+ * fixed chunk length and seen >= R, stays correct on replay; the host copy is
+ * then advanced with dedisp_beam_advance).  Allocates nchans * R * 4 + 8
+ * bytes on the plan's device. */
 mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out);
 mb_status dedisp_beam_destroy(mb_beam* beam);
-/* Forgets the stream history (the next chunk is the first). Host-only. */
+/* Forgets the stream history (the next chunk is the first).  Waits for the
+ * device to be idle. */
 mb_status dedisp_beam_reset(mb_beam* beam);
+/* Advances the host-side sample count by nsamps without launching anything:
+ * for chunks enqueued by replaying a captured graph. */
+mb_status dedisp_beam_advance(mb_beam* beam, int64_t nsamps);
 mb_status dedisp_beam_position(const mb_beam* beam, int64_t* seen);
 
 /* ---- event detection (Sec. 2.3) ---------------------------------------- */

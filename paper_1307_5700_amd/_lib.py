@@ -52,6 +52,11 @@ class RfiLayout(ctypes.Structure):
                 ("masked_u8", c_sz), ("nchunks", c_i64)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", c_vp), ("beam", c_vp), ("d_in", c_vp), ("nsamps", c_i64), ("ld", c_i64),
+                ("d_rfi_state", c_vp), ("d_out", c_vp), ("ld_out", c_i64), ("d_norm", c_vp)]
+
+
 class ExecInfo(ctypes.Structure):
     _fields_ = [("nout", c_i64), ("sample0", c_i64)]
 
@@ -75,6 +80,10 @@ _SIGS = {
     "dedisp_beam_create": ([c_vp, ctypes.POINTER(c_vp)], c_i32),
     "dedisp_beam_destroy": ([c_vp], c_i32),
     "dedisp_beam_reset": ([c_vp], c_i32),
+    "dedisp_beam_advance": ([c_vp, c_i64], c_i32),
+    "dedisp_batch_workspace_size": ([c_i32, ctypes.POINTER(c_sz)], c_i32),
+    "dedisp_execute_batch": ([ctypes.POINTER(BatchItem), c_i32, c_vp, c_sz, ctypes.POINTER(ExecInfo),
+                              c_vp], c_i32),
     "dedisp_beam_position": ([c_vp, ctypes.POINTER(c_i64)], c_i32),
     "detect_workspace_size": ([c_vp, ctypes.POINTER(c_sz)], c_i32),
     "detect_candidates": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_vp,

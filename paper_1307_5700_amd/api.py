@@ -225,6 +225,49 @@ class Plan:
         return peaks.cpu().numpy().view(PEAK_DTYPE)
 
 
+def alloc_batch_work(nitems: int, device=None) -> torch.Tensor:
+    n = ctypes.c_size_t()
+    L.check(L.lib().dedisp_batch_workspace_size(int(nitems), ctypes.byref(n)), "dedisp_batch_workspace_size")
+    return _alloc(n.value, device or torch.device("cuda", torch.cuda.current_device()))
+
+
+def execute_batch(jobs, work: torch.Tensor | None = None, stream=None):
+    """One persistent dedispersion launch (per 16 jobs) over many beams.
+
+    jobs: list of dicts with keys plan, x, and optionally rfi_state, out,
+    norm (tensor, True to allocate, False for none) and beam.  Returns a list
+    of (out, norm, nout, sample0) in job order.
+    """
+    n = len(jobs)
+    items = (L.BatchItem * n)()
+    keep = []
+    for i, j in enumerate(jobs):
+        plan, x = j["plan"], j["x"]
+        T, ld = plan._check_input(x)
+        beam = j.get("beam")
+        out = j.get("out")
+        if out is None:
+            seen = beam.position() if beam is not None else 0
+            v = min(seen, plan.max_delay) if beam is not None else 0
+            out = plan.alloc_output(max(v + T - plan.max_delay, 0))
+        norm = j.get("norm", True)
+        if norm is True:
+            norm = plan.alloc_norm()
+        elif norm is False:
+            norm = None
+        st = j.get("rfi_state")
+        items[i] = L.BatchItem(plan._h, beam._h if beam is not None else None, x.data_ptr(), T, ld,
+                               st.data_ptr() if st is not None else None, out.data_ptr(), out.stride(0),
+                               norm.data_ptr() if norm is not None else None)
+        keep.append((out, norm))
+    if work is None:
+        work = alloc_batch_work(n, jobs[0]["plan"].device)
+    infos = (L.ExecInfo * n)()
+    L.check(L.lib().dedisp_execute_batch(items, n, _ptr(work), work.numel(), infos, _stream_ptr(stream)),
+            "dedisp_execute_batch")
+    return [(keep[i][0], keep[i][1], infos[i].nout, infos[i].sample0) for i in range(n)]
+
+
 class Beam:
     """Device-resident streaming state of one beam (overlap ring)."""
 
@@ -243,6 +286,10 @@ class Beam:
     def reset(self):
         L.check(L.lib().dedisp_beam_reset(self._h), "dedisp_beam_reset")
 
+    def advance(self, nsamps: int):
+        """Host-side bookkeeping for chunks enqueued by a graph replay."""
+        L.check(L.lib().dedisp_beam_advance(self._h, int(nsamps)), "dedisp_beam_advance")
+
     def close(self):
         if getattr(self, "_h", None):
             L.lib().dedisp_beam_destroy(self._h)
@@ -253,3 +300,61 @@ class Beam:
             self.close()
         except Exception:
             pass
+
+
+class ChunkGraph:
+    """One chunk step captured as a HIP graph on fixed buffers and replayed.
+
+    The step is the RFI pass (optional), dedispersion with normalisation and
+    detection, for one plan and an input buffer of fixed shape.  Before each
+    replay the caller writes the next chunk into ``x``; after it, ``out``,
+    ``norm`` and the detection buffers hold that chunk's results.
+
+    With a beam, capture only once the beam is in steady state (it has seen
+    at least one ring of samples, see include/mbtp.h) and keep the chunk
+    length fixed: the ring position is read on the device at run time, and
+    replay() keeps the beam's host-side sample count in step.
+    """
+
+    def __init__(self, plan: Plan, x: torch.Tensor, rfi: bool = True, beam: "Beam | None" = None,
+                 nsigma: float = 6.0, capacity: int = 1 << 16):
+        self.plan, self.x, self.beam, self.nsigma = plan, x, beam, float(nsigma)
+        T, _ = plan._check_input(x)
+        self.T = T
+        if beam is not None:
+            if T % 4 or beam.position() < ((plan.max_delay + 3) // 4) * 4:
+                raise ValueError("capture a beam's step in steady state with a chunk length multiple of 4")
+            self.nout = T
+        else:
+            self.nout = T - plan.max_delay
+        self.state = plan.alloc_rfi_state(T) if rfi else None
+        self.out = plan.alloc_output(self.nout)
+        self.norm = plan.alloc_norm()
+        self.det = plan.alloc_detect(capacity)
+        self.stream = torch.cuda.Stream(device=plan.device)
+        self.graph = torch.cuda.CUDAGraph()
+        self.sample0 = None
+        self._first = True
+        torch.cuda.synchronize(plan.device)
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self._enqueue()
+
+    def _enqueue(self):
+        p = self.plan
+        if self.state is not None:
+            p.rfi_threshold(self.x, self.state)
+        _, _, nout, s0 = p.execute(self.x, rfi_state=self.state, out=self.out, norm=self.norm,
+                                   beam=self.beam)
+        assert nout == self.nout
+        p.detect(self.out, nout, self.norm, self.nsigma, sample0=s0, buffers=self.det)
+        self.sample0 = s0
+
+    def replay(self):
+        """Runs the captured step on the current contents of ``x``; returns the
+        absolute index of the chunk's first output sample."""
+        if self.beam is not None and not self._first:
+            self.beam.advance(self.T)
+            self.sample0 += self.T
+        self._first = False
+        self.graph.replay()
+        return self.sample0

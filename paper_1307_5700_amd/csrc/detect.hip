@@ -5,10 +5,10 @@
 //         sum D^2 in FP64; the least-squares line follows in closed form.
 //         Pass 2 forms the residual sum of squares.  Rows are read twice;
 //         the second read mostly hits the L2 / MALL.
-// detect: pass A counts z > nsigma per row and finds the row's peak; a
-//         single-workgroup exclusive scan turns counts into output offsets;
-//         pass B writes the triplets in (DM, sample) order with ballots.
-// z = (D - a - b t) / sigma is formed in FP64 the same way in both passes.
+// detect: pass A counts z > nsigma per (row, quarter-row segment) and finds
+//         the row's peak; a single-workgroup exclusive scan turns counts into
+//         output offsets; pass B rescans only the segments with hits and
+//         writes the triplets in (DM, sample) order with wave ballots.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -89,71 +89,87 @@ __global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out
   }
 }
 
-__device__ inline double zval(const float* row, int64_t t, const NormDev& n) {
-  if (n.degenerate) return 0.0;
-  return (((double)row[t] - n.a) - n.b * (double)t) / n.sigma;
+// Residual of sample t from the row's line, formed in FP64 with separate
+// roundings: r = (D - a) - b t.  z = r / sigma.  The threshold test z > nsigma
+// is taken as r > nsigma * sigma (the same comparison in both passes; it can
+// differ from the quotient only for z within rounding of nsigma).
+__device__ inline double resid(const float* row, int64_t t, const NormDev& n) {
+  return __dsub_rn(__dsub_rn((double)row[t], n.a), __dmul_rn(n.b, (double)t));
 }
 
-// Pass A: count and peak per row.
+// Each row is split into 4 contiguous segments, one per wave of the block;
+// lanes step through a segment 64 samples at a time.
+__device__ inline void wave_segment(int64_t nout, int w, int64_t& lo, int64_t& hi) {
+  const int64_t seg = ((nout + 255) / 256) * 64;      // multiple of 64
+  lo = min(nout, (int64_t)w * seg);
+  hi = min(nout, lo + seg);
+}
+
+// Pass A: hits per (row, wave segment) and the row's peak.
 __global__ __launch_bounds__(256) void detect_count_kernel(const float* __restrict__ out,
                                                            int64_t ld_out, int64_t nout,
                                                            const NormDev* __restrict__ norm,
                                                            double nsigma, int64_t sample0,
                                                            int64_t* __restrict__ counts,
                                                            PeakDev* __restrict__ peaks) {
-  __shared__ double shz[4];
+  __shared__ double shr[4];
   __shared__ int64_t sht[4];
-  __shared__ int64_t shc[4];
   const int d = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float* row = out + (int64_t)d * ld_out;
   const NormDev n = norm[d];
+  const double thr = nsigma * n.sigma;
+  int64_t lo, hi;
+  wave_segment(nout, wave, lo, hi);
   int64_t cnt = 0;
   double best = -INFINITY;
   int64_t bt = INT64_MAX;
-  for (int64_t t = threadIdx.x; t < nout; t += 256) {
-    const double z = zval(row, t, n);
-    cnt += (z > nsigma) ? 1 : 0;
-    if (z > best) { best = z; bt = t; }   // ascending t per thread: keeps the earliest
+  if (!n.degenerate) {
+    for (int64_t t = lo + lane; t < hi; t += 64) {
+      const double r = resid(row, t, n);
+      cnt += (r > thr) ? 1 : 0;
+      if (r > best) { best = r; bt = t; }     // ascending t per lane keeps the earliest
+    }
   }
-  // wave reduction: (max z, min t)
   for (int off = 32; off >= 1; off >>= 1) {
-    const double oz = __shfl_xor(best, off, 64);
+    const double ob = __shfl_xor(best, off, 64);
     const int64_t ot = __shfl_xor(bt, off, 64);
-    const int64_t oc = __shfl_xor(cnt, off, 64);
-    cnt += oc;
-    if (oz > best || (oz == best && ot < bt)) { best = oz; bt = ot; }
+    cnt += __shfl_xor(cnt, off, 64);
+    if (ob > best || (ob == best && ot < bt)) { best = ob; bt = ot; }
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { shz[w] = best; sht[w] = bt; shc[w] = cnt; }
+  if (lane == 0) {
+    counts[(int64_t)d * 4 + wave] = cnt;
+    shr[wave] = best;
+    sht[wave] = bt;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double bz = shz[0];
-    int64_t btt = sht[0];
-    int64_t c = shc[0];
-    for (int k = 1; k < 4; ++k) {
-      c += shc[k];
-      if (shz[k] > bz || (shz[k] == bz && sht[k] < btt)) { bz = shz[k]; btt = sht[k]; }
+  if (threadIdx.x == 0 && peaks) {
+    PeakDev p;
+    p.reserved = 0;
+    if (n.degenerate || nout == 0) {
+      p.sample = sample0;
+      p.snr = 0.0f;
+    } else {
+      double br = shr[0];
+      int64_t btt = sht[0];
+      for (int k = 1; k < 4; ++k)
+        if (shr[k] > br || (shr[k] == br && sht[k] < btt)) { br = shr[k]; btt = sht[k]; }
+      p.sample = sample0 + btt;
+      p.snr = (float)(br / n.sigma);
     }
-    counts[d] = c;
-    if (peaks) {
-      PeakDev p;
-      p.sample = sample0 + (nout > 0 ? btt : 0);
-      p.snr = nout > 0 ? (float)bz : 0.0f;
-      p.reserved = 0;
-      peaks[d] = p;
-    }
+    peaks[d] = p;
   }
 }
 
-// Exclusive scan of the per-row counts (one 1024-thread workgroup).
+// Exclusive scan of the per-(row, segment) counts (one 1024-thread workgroup).
 __global__ __launch_bounds__(1024) void detect_scan_kernel(const int64_t* __restrict__ counts,
-                                                           int32_t ndms, int64_t* __restrict__ offsets,
+                                                           int64_t n, int64_t* __restrict__ offsets,
                                                            int64_t* __restrict__ total) {
   __shared__ int64_t sh[1024];
   int64_t carry = 0;
-  for (int32_t base = 0; base < ndms; base += 1024) {
-    const int32_t i = base + threadIdx.x;
-    const int64_t v = (i < ndms) ? counts[i] : 0;
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = (i < n) ? counts[i] : 0;
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -162,58 +178,61 @@ __global__ __launch_bounds__(1024) void detect_scan_kernel(const int64_t* __rest
       sh[threadIdx.x] += add;
       __syncthreads();
     }
-    if (i < ndms) offsets[i] = carry + sh[threadIdx.x] - v;
-    carry += sh[1023];
+    if (i < n) offsets[i] = carry + sh[threadIdx.x] - v;
+    const int64_t blk = sh[1023];
     __syncthreads();
+    carry += blk;
   }
   if (threadIdx.x == 0) *total = carry;
 }
 
-// Pass B: write the triplets of each row in sample order.
+// Pass B: each wave rescans its segment (only if it holds hits) and writes
+// them in sample order: ballot + popcount within 64 samples, a running
+// offset across them.  No barriers.
 __global__ __launch_bounds__(256) void detect_write_kernel(const float* __restrict__ out,
                                                            int64_t ld_out, int64_t nout,
                                                            const NormDev* __restrict__ norm,
                                                            double nsigma, int64_t sample0,
                                                            double dm_start, double dm_step,
+                                                           const int64_t* __restrict__ counts,
                                                            const int64_t* __restrict__ offsets,
                                                            CandDev* __restrict__ cands,
                                                            int64_t capacity) {
-  __shared__ int wcount[4];
   const int d = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)d * 4 + wave;
+  if (counts[slot] == 0) return;
+  int64_t pos = offsets[slot];
+  if (pos >= capacity) return;
   const float* row = out + (int64_t)d * ld_out;
   const NormDev n = norm[d];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double thr = nsigma * n.sigma;
   const float dmv = (float)(dm_start + (double)d * dm_step);
-  int64_t pos = offsets[d];
-  for (int64_t t0 = 0; t0 < nout; t0 += 256) {
-    const int64_t t = t0 + threadIdx.x;
-    double z = 0.0;
+  int64_t lo, hi;
+  wave_segment(nout, wave, lo, hi);
+  for (int64_t t0 = lo; t0 < hi; t0 += 64) {
+    const int64_t t = t0 + lane;
+    double r = 0.0;
     bool hit = false;
-    if (t < nout) {
-      z = zval(row, t, n);
-      hit = z > nsigma;
+    if (t < hi) {
+      r = resid(row, t, n);
+      hit = r > thr;
     }
     const unsigned long long bal = __ballot(hit);
-    if (lane == 0) wcount[wave] = __popcll(bal);
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < wave; ++k) before += wcount[k];
-    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
     if (hit) {
       const unsigned long long lower = (lane == 0) ? 0ull : (bal & ((1ull << lane) - 1ull));
-      const int64_t k = pos + before + __popcll(lower);
+      const int64_t k = pos + __popcll(lower);
       if (k < capacity) {
         CandDev cd;
         cd.dm_index = d;
         cd.reserved = 0;
         cd.sample = sample0 + t;
-        cd.snr = (float)z;
+        cd.snr = (float)(r / n.sigma);
         cd.dm = dmv;
         cands[k] = cd;
       }
     }
-    pos += total;
-    __syncthreads();
+    pos += __popcll(bal);
   }
 }
 
@@ -230,12 +249,13 @@ hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t
                          double dm_step, CandDev* cands, int64_t capacity, int64_t* d_count,
                          PeakDev* peaks, void* work, hipStream_t s) {
   int64_t* counts = static_cast<int64_t*>(work);
-  int64_t* offsets = counts + ndms + 1;
+  int64_t* offsets = counts + 4 * (int64_t)ndms;
   hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)ndms), dim3(256), 0, s, out, ld_out, nout,
                      norm, nsigma, sample0, counts, peaks);
-  hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(1024), 0, s, counts, ndms, offsets, d_count);
+  hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(1024), 0, s, counts, 4 * (int64_t)ndms,
+                     offsets, d_count);
   hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)ndms), dim3(256), 0, s, out, ld_out, nout,
-                     norm, nsigma, sample0, dm_start, dm_step, offsets, cands, capacity);
+                     norm, nsigma, sample0, dm_start, dm_step, counts, offsets, cands, capacity);
   return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ static_assert(sizeof(RfiHeader) <= 256, "header too large");
 struct RfiGeom {
   int64_t C, T, W, J, nspans, CG, ngroups;
   size_t off_hdr, off_fit, off_fit32, off_bsum, off_binterp, off_span, off_chunk, off_spart;
-  size_t off_flags, off_lcount, off_list, off_gflags, off_masked, total;
+  size_t off_flags, off_lcount, off_list, off_gflags, off_masked, off_cbits, off_gspan, total;
+  int64_t JW;                // 32-bit words per channel of the chunk-flag bitmask
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -66,6 +67,9 @@ inline RfiGeom rfi_geometry(int64_t C, int64_t T, int64_t W) {
   g.off_list = o;     o = align256(o + sizeof(int32_t) * C * g.J);
   g.off_gflags = o;   o = align256(o + size_t(T));
   g.off_masked = o;   o = align256(o + size_t(C));
+  g.JW = (g.J + 31) / 32;
+  g.off_cbits = o;    o = align256(o + sizeof(uint32_t) * C * g.JW);
+  g.off_gspan = o;    o = align256(o + sizeof(int32_t) * (g.nspans + 1));
   g.total = o;
   return g;
 }
@@ -83,9 +87,12 @@ struct CleanView {
   const double* fit;         // f[C]
   const uint8_t* cflags;     // [C][J], bit1 = flagged after extension
   const uint8_t* gflags;     // [T]
+  const uint32_t* cbits;     // [C][JW]: bit j%32 of word j/32 = chunk j flagged (extended)
+  const int32_t* gspan;      // [nspans+1]: flagged spectra before each 256-sample span
+  int64_t JW, nspans;
   int64_t J;
   uint32_t W;
-  int32_t wshift;            // log2(W) when W is a power of two, else -1
+  int32_t wshift;            // log2(W)
 };
 
 // Everything one dedispersion launch needs.
@@ -112,12 +119,34 @@ struct DedispArgs {
   int32_t n_dblocks, n_ttiles;
   int32_t rs;                // LDS copy length in floats (multiple of 4)
   int32_t relb_ld;           // row stride of the relb table (channels rounded up to 4)
+  int32_t zero;              // always 0: gives per-row loads a lane-dependent address so
+                             // they are vector loads, never scalar ones
+  const int64_t* seen_dev;   // beam's device-side sample count (ring position), or null
 };
 
+// One item of a batched persistent launch, and the launch's arguments
+// (passed by value: at most kMaxBatch items, within the 4 KiB argument limit).
+constexpr int kMaxBatch = 16;
+struct BatchItem {
+  DedispArgs a;
+  const int32_t* relb;
+  const float* fit32;
+  int32_t tile0;             // first global tile of this item
+  int32_t pad;
+};
+struct BatchArgs {
+  BatchItem item[kMaxBatch];
+  int32_t nitems, total;
+  int* counter;              // zeroed by the launcher before the launch
+};
+static_assert(sizeof(BatchArgs) <= 4096, "batch arguments exceed the kernel argument limit");
+
 struct Tiling {
-  int G, Q, BC;   // DMs per wave, float4 groups per lane, channels per LDS stage
-  int BD() const { return 4 * G; }
+  int NW, G, Q, BC;   // waves per workgroup, DMs per wave, float4 groups per lane,
+                      // channels per LDS stage
+  int BD() const { return NW * G; }
   int BT() const { return 256 * Q; }
+  int threads() const { return 64 * NW; }
 };
 
 // Quads of staged samples each thread prefetches per channel block.
@@ -135,10 +164,16 @@ hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, cons
                          const int32_t* relb, const float* fit32, size_t lds_bytes,
                          hipStream_t s);
 
-// Writes the chunk's last min(L, R) cleaned samples into the ring.
+// One persistent launch over the tiles of all items (same dtype, cleaning
+// and tiling); lds = the largest item's LDS.
+hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds,
+                               hipStream_t s);
+
+// Writes the chunk's last min(L, R) cleaned samples into the ring at the
+// positions given by the beam's device-side sample count, then advances it.
 hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, int64_t L,
                               int32_t C, const CleanView& cv, const float* fit32, float* ring,
-                              int64_t R, int64_t seen, hipStream_t s);
+                              int64_t R, int64_t* seen_dev, hipStream_t s);
 
 struct NormDev { double a, b, sigma; int32_t degenerate, reserved; };
 struct CandDev { int32_t dm_index, reserved; int64_t sample; float snr, dm; };
@@ -153,7 +188,7 @@ hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t
                          int64_t* d_count, PeakDev* peaks, void* work, hipStream_t s);
 
 inline size_t detect_work_bytes(int32_t ndms) {
-  return align256(sizeof(int64_t) * 2 * (size_t(ndms) + 1));
+  return align256(sizeof(int64_t) * 8 * size_t(ndms));   // counts and offsets per (row, segment)
 }
 
 }  // namespace mbtp

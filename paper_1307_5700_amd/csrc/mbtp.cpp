@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -88,7 +89,7 @@ struct mb_plan {
   std::vector<int32_t> h_delays;
   int32_t* d_delays = nullptr;
   int32_t* d_relb = nullptr;
-  Tiling tiling{8, 2, 4};
+  Tiling tiling{4, 4, 2, 4};
   int rs = 0;
   size_t lds = 0;
   int n_dblocks = 0;
@@ -98,6 +99,7 @@ struct mb_plan {
 struct mb_beam {
   const mb_plan* plan = nullptr;
   float* d_ring = nullptr;
+  int64_t* d_seen = nullptr;   // device-side sample count: the ring position kernels read
   int64_t R = 0;
   int64_t seen = 0;
 };
@@ -118,7 +120,7 @@ int32_t span_max(const mb_plan& p, int BD) {
   return m;
 }
 
-constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kMaxLds = 160 * 1024;   // gfx950 LDS per workgroup
 
 // LDS copy length: the largest window start (span + 3, rounded down to 4)
 // plus the tile, plus the quad read after the last one.
@@ -132,7 +134,7 @@ void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
 // A tiling fits when its LDS fits and each lane's prefetch registers cover
 // its share of a channel block.
 bool tiling_fits(const Tiling& t, int rs, size_t lds) {
-  const int rows_per_wave = t.BC / 4;
+  const int rows_per_wave = t.NW >= t.BC ? 1 : t.BC / t.NW;
   const int quads_per_lane = ((rs / 4) + 63) / 64;
   return lds <= kMaxLds && rows_per_wave * quads_per_lane <= kStageQuads;
 }
@@ -164,8 +166,8 @@ mb_status choose_tiling(mb_plan& p) {
 
 mb_status validate_rfi(const mb_rfi_params& r, int C) {
   if (r.poly_order < 0 || r.poly_order > 8) return fail(MB_EINVAL, "rfi.poly_order %d not in 0..8", r.poly_order);
-  if (r.window <= 0 || r.window % kSpan != 0)
-    return fail(MB_EINVAL, "rfi.window %d must be a positive multiple of %d", r.window, kSpan);
+  if (r.window < kSpan || (r.window & (r.window - 1)) != 0)
+    return fail(MB_EINVAL, "rfi.window %d must be a power of two >= %d", r.window, kSpan);
   if (!(r.k_mask > 0) || !(r.k_chan > 0) || !(r.k_spec > 0))
     return fail(MB_EINVAL, "rfi threshold factors must be positive");
   if (r.mask_passes < 1 || r.mask_passes > 16) return fail(MB_EINVAL, "rfi.mask_passes %d not in 1..16", r.mask_passes);
@@ -362,6 +364,14 @@ mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out) {
       return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
   }
+  const int64_t zero = 0;
+  if (hipMalloc(&b->d_seen, sizeof(int64_t)) != hipSuccess ||
+      hipMemcpy(b->d_seen, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(b->d_ring);
+    (void)hipFree(b->d_seen);
+    delete b;
+    return fail(MB_ENOMEM, "beam state allocation failed");
+  }
   *out = b;
   return ok();
 }
@@ -369,13 +379,23 @@ mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out) {
 mb_status dedisp_beam_destroy(mb_beam* beam) {
   if (!beam) return ok();
   (void)hipFree(beam->d_ring);
+  (void)hipFree(beam->d_seen);
   delete beam;
   return ok();
 }
 
 mb_status dedisp_beam_reset(mb_beam* beam) {
   if (!beam) return fail(MB_EINVAL, "beam is NULL");
+  const int64_t zero = 0;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(beam->d_seen, &zero, sizeof(zero), hipMemcpyHostToDevice));
   beam->seen = 0;
+  return ok();
+}
+
+mb_status dedisp_beam_advance(mb_beam* beam, int64_t nsamps) {
+  if (!beam || nsamps < 0 || nsamps % 4 != 0) return fail(MB_EINVAL, "beam non-NULL, nsamps >= 0 and a multiple of 4");
+  beam->seen += nsamps;
   return ok();
 }
 
@@ -385,9 +405,28 @@ mb_status dedisp_beam_position(const mb_beam* beam, int64_t* seen) {
   return ok();
 }
 
-mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t nsamps,
-                         int64_t ld, const void* d_rfi_state, float* d_out, int64_t ld_out,
-                         mb_norm* d_norm, mb_exec_info* info, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One item of an execute call, validated and turned into launch arguments.
+struct Prepared {
+  const mb_plan* plan;
+  mb_beam* beam;
+  const void* d_in;
+  int64_t nsamps, ld;
+  bool clean;
+  CleanView cv;
+  const float* fit32;
+  DedispArgs a;
+  float* d_out;
+  int64_t ld_out;
+  mb_norm* d_norm;
+  int64_t nout, sample0;
+};
+
+mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t nsamps, int64_t ld,
+                  const void* d_rfi_state, float* d_out, int64_t ld_out, mb_norm* d_norm, Prepared& P) {
   mb_status st = validate_input(plan, d_in, nsamps, ld);
   if (st) return st;
   if (beam && beam->plan != plan) return fail(MB_EINVAL, "beam was created from another plan");
@@ -411,60 +450,162 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, i
       return fail(MB_EINVAL, "ld_out (%lld) must be >= nout (%lld) and a multiple of 4", (long long)ld_out, (long long)nout_c);
   }
   if (d_norm && !check_aligned(d_norm, 8)) return fail(MB_EINVAL, "norm must be 8-byte aligned");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool clean = d_rfi_state != nullptr;
-  CleanView cv{};
-  const float* fit32 = nullptr;
-  if (clean) {
+  P = Prepared{};
+  P.plan = plan;
+  P.beam = beam;
+  P.d_in = d_in;
+  P.nsamps = nsamps;
+  P.ld = ld;
+  P.clean = d_rfi_state != nullptr;
+  P.d_out = d_out;
+  P.ld_out = ld_out;
+  P.d_norm = d_norm;
+  P.nout = nout_c;
+  P.sample0 = seen - veff;
+  if (P.clean) {
     const RfiGeom g = rfi_geometry(plan->desc.nchans, nsamps, plan->desc.rfi.window);
     const char* stp = static_cast<const char*>(d_rfi_state);
+    CleanView& cv = P.cv;
     cv.fit = reinterpret_cast<const double*>(stp + g.off_fit);
     cv.cflags = reinterpret_cast<const uint8_t*>(stp + g.off_flags);
     cv.gflags = reinterpret_cast<const uint8_t*>(stp + g.off_gflags);
     cv.J = g.J;
+    cv.cbits = reinterpret_cast<const uint32_t*>(stp + g.off_cbits);
+    cv.gspan = reinterpret_cast<const int32_t*>(stp + g.off_gspan);
+    cv.JW = g.JW;
+    cv.nspans = g.nspans;
     cv.W = (uint32_t)plan->desc.rfi.window;
-    cv.wshift = -1;
-    for (int k = 0; k < 31; ++k)
-      if ((1u << k) == cv.W) cv.wshift = k;
-    fit32 = reinterpret_cast<const float*>(stp + g.off_fit32);
+    cv.wshift = 0;
+    while ((1u << cv.wshift) < cv.W) ++cv.wshift;
+    P.fit32 = reinterpret_cast<const float*>(stp + g.off_fit32);
   }
-  const int64_t sample0 = seen - veff;
-  if (nout_c > 0) {
-    DedispArgs a{};
-    a.x = d_in;
-    a.ld = ld;
-    a.L = nsamps;
-    a.ring = beam ? beam->d_ring : nullptr;
-    a.R = R;
-    a.ring_valid = v;
-    a.ring_p0 = (R > 0) ? (seen - v) % R : 0;
-    a.phase = phase;
-    a.delays = plan->d_delays;
-    a.C = plan->desc.nchans;
-    a.ndms = plan->desc.ndms;
-    a.nout = nout_c;
-    a.out = d_out;
-    a.ld_out = ld_out;
-    a.clean = cv;
-    a.n_dblocks = plan->n_dblocks;
-    a.n_ttiles = (int32_t)((phase + nout_c + plan->tiling.BT() - 1) / plan->tiling.BT());
-    a.rs = plan->rs;
-    a.relb_ld = plan->relb_ld;
-    HIP_TRY(launch_dedisp(plan->desc.in_dtype, clean, beam != nullptr && v > 0, plan->tiling, a, plan->d_relb, fit32,
-                          plan->lds, s));
+  DedispArgs& A = P.a;
+  A.x = d_in;
+  A.ld = ld;
+  A.L = nsamps;
+  A.ring = beam ? beam->d_ring : nullptr;
+  A.R = R;
+  A.ring_valid = v;
+  A.ring_p0 = (R > 0) ? (seen - v) % R : 0;
+  A.phase = phase;
+  A.delays = plan->d_delays;
+  A.C = plan->desc.nchans;
+  A.ndms = plan->desc.ndms;
+  A.nout = nout_c;
+  A.out = d_out;
+  A.ld_out = ld_out;
+  A.clean = P.cv;
+  A.n_dblocks = plan->n_dblocks;
+  A.n_ttiles = (int32_t)((phase + nout_c + plan->tiling.BT() - 1) / plan->tiling.BT());
+  A.rs = plan->rs;
+  A.relb_ld = plan->relb_ld;
+  A.zero = 0;
+  A.seen_dev = beam ? beam->d_seen : nullptr;
+  return MB_OK;
+}
+
+// Normalisation and ring update of a prepared item, after its dedispersion.
+mb_status finish_item(Prepared& P, hipStream_t s) {
+  const mb_plan* plan = P.plan;
+  if (P.d_norm)
+    HIP_TRY(launch_norm(P.d_out, P.ld_out, P.nout, plan->desc.ndms, reinterpret_cast<NormDev*>(P.d_norm), s));
+  if (P.beam) {
+    HIP_TRY(launch_ring_update(plan->desc.in_dtype, P.clean, P.d_in, P.ld, P.nsamps, plan->desc.nchans,
+                               P.cv, P.fit32, P.beam->d_ring, P.beam->R, P.beam->d_seen, s));
+    P.beam->seen += P.nsamps;
   }
-  if (d_norm) {
-    HIP_TRY(launch_norm(d_out, ld_out, nout_c, plan->desc.ndms, reinterpret_cast<NormDev*>(d_norm), s));
-  }
-  if (beam) {
-    if (R > 0)
-      HIP_TRY(launch_ring_update(plan->desc.in_dtype, clean, d_in, ld, nsamps, plan->desc.nchans, cv,
-                                 fit32, beam->d_ring, R, beam->seen, s));
-    beam->seen += nsamps;
-  }
+  return MB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t nsamps,
+                         int64_t ld, const void* d_rfi_state, float* d_out, int64_t ld_out,
+                         mb_norm* d_norm, mb_exec_info* info, void* stream) {
+  Prepared P;
+  mb_status st = prepare(plan, beam, d_in, nsamps, ld, d_rfi_state, d_out, ld_out, d_norm, P);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (P.nout > 0)
+    HIP_TRY(launch_dedisp(plan->desc.in_dtype, P.clean, beam != nullptr && P.a.ring_valid > 0, plan->tiling,
+                          P.a, plan->d_relb, P.fit32, plan->lds, s));
+  st = finish_item(P, s);
+  if (st) return st;
   if (info) {
-    info->nout = nout_c;
-    info->sample0 = sample0;
+    info->nout = P.nout;
+    info->sample0 = P.sample0;
+  }
+  return ok();
+}
+
+mb_status dedisp_batch_workspace_size(int32_t nitems, size_t* bytes) {
+  if (!bytes || nitems < 1) return fail(MB_EINVAL, "nitems must be >= 1 and bytes non-NULL");
+  *bytes = 256 * (size_t)((nitems + kMaxBatch - 1) / kMaxBatch);
+  return ok();
+}
+
+mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void* d_work,
+                               size_t work_bytes, mb_exec_info* infos, void* stream) {
+  if (!items || nitems < 1) return fail(MB_EINVAL, "items must be non-NULL and nitems >= 1");
+  const int32_t nlaunch = (nitems + kMaxBatch - 1) / kMaxBatch;
+  if (!d_work || !check_aligned(d_work, 256) || work_bytes < 256 * (size_t)nlaunch)
+    return fail(MB_EINVAL, "workspace must be 256-byte aligned with %zu bytes", 256 * (size_t)nlaunch);
+  std::vector<Prepared> P(nitems);
+  const mb_plan* p0 = items[0].plan;
+  if (!p0) return fail(MB_EINVAL, "item 0 has no plan");
+  const bool clean0 = items[0].d_rfi_state != nullptr;
+  for (int32_t i = 0; i < nitems; ++i) {
+    const mb_batch_item& it = items[i];
+    if (!it.plan) return fail(MB_EINVAL, "item %d has no plan", i);
+    if (it.plan->desc.in_dtype != p0->desc.in_dtype)
+      return fail(MB_EINVAL, "item %d: all items of a batch share the storage type", i);
+    const Tiling& t = it.plan->tiling;
+    if (t.NW != p0->tiling.NW || t.G != p0->tiling.G || t.Q != p0->tiling.Q || t.BC != p0->tiling.BC)
+      return fail(MB_EINVAL, "item %d: all plans of a batch must use the same tiling (tile_hint)", i);
+    if ((it.d_rfi_state != nullptr) != clean0)
+      return fail(MB_EINVAL, "item %d: either every item or none has an RFI state", i);
+    for (int32_t j = 0; j < i; ++j)
+      if (it.beam && it.beam == items[j].beam) return fail(MB_EINVAL, "item %d: a beam appears twice", i);
+    mb_status st = prepare(it.plan, it.beam, it.d_in, it.nsamps, it.ld, it.d_rfi_state, it.d_out,
+                           it.ld_out, it.d_norm, P[i]);
+    if (st) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // heaviest tiles first: cost of a tile grows with its channel count
+  std::vector<int32_t> order(nitems);
+  for (int32_t i = 0; i < nitems; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return P[x].plan->desc.nchans > P[y].plan->desc.nchans;
+  });
+  for (int32_t l = 0; l < nlaunch; ++l) {
+    BatchArgs b;
+    memset(&b, 0, sizeof(b));
+    b.counter = reinterpret_cast<int*>(static_cast<char*>(d_work) + 256 * (size_t)l);
+    size_t lds = 0;
+    int32_t total = 0;
+    for (int32_t k = l * kMaxBatch; k < nitems && k < (l + 1) * kMaxBatch; ++k) {
+      const Prepared& q = P[order[k]];
+      if (q.nout <= 0) continue;
+      BatchItem& bi = b.item[b.nitems++];
+      bi.a = q.a;
+      bi.relb = q.plan->d_relb;
+      bi.fit32 = q.fit32;
+      bi.tile0 = total;
+      total += q.a.n_dblocks * q.a.n_ttiles;
+      if (q.plan->lds > lds) lds = q.plan->lds;
+    }
+    b.total = total;
+    if (total > 0) HIP_TRY(launch_dedisp_batch(p0->desc.in_dtype, clean0, p0->tiling, b, lds, s));
+  }
+  for (int32_t i = 0; i < nitems; ++i) {
+    mb_status st = finish_item(P[i], s);
+    if (st) return st;
+    if (infos) {
+      infos[i].nout = P[i].nout;
+      infos[i].sample0 = P[i].sample0;
+    }
   }
   return ok();
 }

@@ -148,34 +148,49 @@ __device__ inline double u_of(int64_t c, int64_t C) {
   return (2.0 * (double)c - (double)(C - 1)) / (double)(C - 1);
 }
 
-// Fits values v[c] (global), writes the fitted curve to fit[c]; returns RMSE
-// of v - fit.  All threads of the block call it.
-__device__ double fit_poly(const double* v, int64_t C, int p, double* fit, double* sh,
-                           double* coef_sh) {
+// Block-wide sums of NV values per thread at once (1024 threads): each wave
+// reduces its values, then thread k < NV adds the 16 wave results of value k.
+// Fixed order; two barriers for the whole batch.
+template <int NV>
+__device__ inline void block_sums_1024(const double (&v)[NV], double* sh /* 16*NV + NV */,
+                                       double (&out)[NV]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double r = wave_sum(v[k]);
+    if (lane == 0) sh[w * NV + k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double t = 0.0;
+    for (int ww = 0; ww < 16; ++ww) t += sh[ww * NV + threadIdx.x];
+    sh[16 * NV + threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = sh[16 * NV + k];
+}
+
+constexpr int kNG = (kMaxP + 1) * (kMaxP + 2) / 2;   // packed lower Gram entries
+
+// Cholesky factor (packed lower, in L) of the Legendre Gram matrix of degree
+// p over the C channel positions.  All threads call it.
+__device__ void gram_cholesky(int64_t C, int p, double* sh, double* L) {
   const int n = p + 1;
-  double Gl[(kMaxP + 1) * (kMaxP + 2) / 2];
-  double hl[kMaxP + 1];
-  for (int i = 0; i < (kMaxP + 1) * (kMaxP + 2) / 2; ++i) Gl[i] = 0.0;
-  for (int i = 0; i <= kMaxP; ++i) hl[i] = 0.0;
+  double Gl[kNG];
+  for (int i = 0; i < kNG; ++i) Gl[i] = 0.0;
   double P[kMaxP + 1];
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     legendre(u_of(c, C), p, P);
-    const double vc = v[c];
     int k = 0;
-    for (int i = 0; i < n; ++i) {
-      hl[i] += P[i] * vc;
-      for (int j = 0; j <= i; ++j) Gl[k++] += P[i] * P[j];
-    }
+    for (int i = 0; i <= kMaxP; ++i)
+      for (int j = 0; j <= i; ++j, ++k)
+        if (i < n) Gl[k] += P[i] * P[j];
   }
-  // reduce the n(n+1)/2 Gram entries and n right-hand sides
-  double G[(kMaxP + 1) * (kMaxP + 2) / 2];
-  double h[kMaxP + 1];
-  const int ng = n * (n + 1) / 2;
-  for (int i = 0; i < ng; ++i) G[i] = block_sum_1024(Gl[i], sh);
-  for (int i = 0; i < n; ++i) h[i] = block_sum_1024(hl[i], sh);
+  double G[kNG];
+  block_sums_1024<kNG>(Gl, sh, G);
   if (threadIdx.x == 0) {
-    // Cholesky G = L L^T (packed lower), then two triangular solves
-    double L[(kMaxP + 1) * (kMaxP + 2) / 2];
     for (int i = 0; i < n; ++i) {
       for (int j = 0; j <= i; ++j) {
         double s = G[i * (i + 1) / 2 + j];
@@ -184,6 +199,27 @@ __device__ double fit_poly(const double* v, int64_t C, int p, double* fit, doubl
         else L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
       }
     }
+  }
+  __syncthreads();
+}
+
+// Least-squares fit of v[c] with the factored Gram matrix: writes the fitted
+// curve to fit[c] and returns the RMSE of v - fit.  All threads call it.
+__device__ double fit_poly(const double* v, int64_t C, int p, const double* L, double* fit,
+                           double* sh, double* coef_sh) {
+  const int n = p + 1;
+  double hl[kMaxP + 1];
+  for (int i = 0; i <= kMaxP; ++i) hl[i] = 0.0;
+  double P[kMaxP + 1];
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    legendre(u_of(c, C), p, P);
+    const double vc = v[c];
+    for (int i = 0; i <= kMaxP; ++i)
+      if (i < n) hl[i] += P[i] * vc;
+  }
+  double h[kMaxP + 1];
+  block_sums_1024<kMaxP + 1>(hl, sh, h);
+  if (threadIdx.x == 0) {
     double y[kMaxP + 1];
     for (int i = 0; i < n; ++i) {
       double s = h[i];
@@ -197,17 +233,18 @@ __device__ double fit_poly(const double* v, int64_t C, int p, double* fit, doubl
     }
   }
   __syncthreads();
-  double ssq = 0.0;
+  double ssq[1] = {0.0};
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     legendre(u_of(c, C), p, P);
     double f = 0.0;
     for (int i = 0; i < n; ++i) f += coef_sh[i] * P[i];
     fit[c] = f;
     const double r = v[c] - f;
-    ssq += r * r;
+    ssq[0] += r * r;
   }
-  const double tot = block_sum_1024(ssq, sh);
-  return sqrt(tot / (double)C);
+  double tot[1];
+  block_sums_1024<1>(ssq, sh, tot);
+  return sqrt(tot[0] / (double)C);
 }
 
 __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, RfiParamsDev prm,
@@ -217,19 +254,20 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
                                                        float* __restrict__ fit32,
                                                        uint8_t* __restrict__ masked,
                                                        RfiHeader* __restrict__ hdr) {
-  __shared__ double sh[32];
+  __shared__ double sh[17 * kNG];
   __shared__ double coef_sh[kMaxP + 1];
+  __shared__ double L[kNG];
   __shared__ int any_left;
   const double invT = 1.0 / (double)T;
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     binterp[c] = bsum[c] * invT;
     masked[c] = 0;
   }
-  __syncthreads();
+  gram_cholesky(C, prm.p, sh, L);   // (its barriers also publish binterp/masked)
   double rmse0 = 0.0;
   int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
   for (int pass = 0; pass < passes; ++pass) {
-    const double rmse_i = fit_poly(binterp, C, prm.p, fit, sh, coef_sh);
+    const double rmse_i = fit_poly(binterp, C, prm.p, L, fit, sh, coef_sh);
     if (pass == 0) rmse0 = rmse_i;
     const double thr = prm.k_mask * rmse_i;
     for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
@@ -270,24 +308,24 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
     }
     return;
   }
-  const double rmse = fit_poly(binterp, C, prm.p, fit, sh, coef_sh);
-  double sf = 0.0, nm = 0.0;
+  const double rmse = fit_poly(binterp, C, prm.p, L, fit, sh, coef_sh);
+  double sums[2] = {0.0, 0.0};
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     fit32[c] = (float)fit[c];
-    sf += fit[c];
-    nm += masked[c] ? 1.0 : 0.0;
+    sums[0] += fit[c];
+    sums[1] += masked[c] ? 1.0 : 0.0;
   }
-  sf = block_sum_1024(sf, sh);
-  nm = block_sum_1024(nm, sh);
+  double tot[2];
+  block_sums_1024<2>(sums, sh, tot);
   if (threadIdx.x == 0) {
     const double sigma = rmse * sqrt((double)T * (double)C / (double)(C - prm.p - 1));
     hdr->sigma = sigma;
     hdr->rmse0 = rmse0;
     hdr->rmse = rmse;
-    hdr->sum_fit = sf;
+    hdr->sum_fit = tot[0];
     hdr->thr_spec = prm.k_spec * sigma / sqrt((double)C);
     hdr->k_chan = prm.k_chan;
-    hdr->n_masked = (unsigned long long)nm;
+    hdr->n_masked = (unsigned long long)tot[1];
     hdr->n_chunk = hdr->n_chunk_ext = hdr->n_spec = 0;
     hdr->error = 0;
   }
@@ -366,7 +404,8 @@ __global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
     const TIN* __restrict__ x, int64_t ld, int64_t C, int64_t T, int64_t W, int64_t J,
     const double* __restrict__ spart, int64_t ngroups, const double* __restrict__ fit,
     const int32_t* __restrict__ lcount, const int32_t* __restrict__ list,
-    RfiHeader* __restrict__ hdr, uint8_t* __restrict__ gflags) {
+    RfiHeader* __restrict__ hdr, uint8_t* __restrict__ gflags, int32_t* __restrict__ span_count) {
+  __shared__ int wc[4];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   bool g = false;
@@ -384,8 +423,54 @@ __global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
     g = fabs(s) > hdr->thr_spec;
   }
   if (t < T) gflags[t] = g ? 1 : 0;
-  unsigned long long cnt = __popcll(__ballot(g));
-  if (lane == 0 && cnt) atomicAdd(&hdr->n_spec, cnt);
+  const int cnt = __popcll(__ballot(g));
+  if (lane == 0) wc[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wc[0] + wc[1] + wc[2] + wc[3];
+    span_count[blockIdx.x] = tot;
+    if (tot) atomicAdd(&hdr->n_spec, (unsigned long long)tot);
+  }
+}
+
+// Tables that let dedispersion staging skip per-sample flag reads: the
+// extended chunk flags as one bit per chunk, and the exclusive prefix count of
+// flagged spectra per 256-sample span (one 1024-thread workgroup scans it).
+__global__ __launch_bounds__(256) void rfi_chunk_bits_kernel(const uint8_t* __restrict__ flags,
+                                                             int64_t C, int64_t J, int64_t JW,
+                                                             uint32_t* __restrict__ cbits) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= C * JW) return;
+  const int64_t c = i / JW, w = i % JW;
+  uint32_t word = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t j = w * 32 + b;
+    if (j < J && (flags[c * J + j] & 2)) word |= 1u << b;
+  }
+  cbits[i] = word;
+}
+
+__global__ __launch_bounds__(1024) void rfi_span_scan_kernel(int32_t* __restrict__ span_count,
+                                                             int64_t nspans) {
+  __shared__ int32_t sh[1024];
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nspans; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = (i < nspans) ? span_count[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nspans) span_count[i] = carry + sh[threadIdx.x] - v;    // exclusive, in place
+    const int32_t blk = sh[1023];
+    __syncthreads();
+    carry += blk;
+  }
+  if (threadIdx.x == 0) span_count[nspans] = carry;
 }
 
 template <typename TIN>
@@ -404,6 +489,8 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
   int32_t* lcount = reinterpret_cast<int32_t*>(st + g.off_lcount);
   int32_t* list = reinterpret_cast<int32_t*>(st + g.off_list);
   RfiHeader* hdr = reinterpret_cast<RfiHeader*>(st + g.off_hdr);
+  uint32_t* cbits = reinterpret_cast<uint32_t*>(st + g.off_cbits);
+  int32_t* gspan = reinterpret_cast<int32_t*>(st + g.off_gspan);
 
   hipLaunchKernelGGL(rfi_stats_kernel<TIN>, dim3((unsigned)g.nspans, (unsigned)g.ngroups),
                      dim3(256), 0, s, x, ld, g.C, g.T, g.nspans, g.CG, span_sum, spart);
@@ -415,7 +502,10 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
                      g.C, g.T, g.W, g.J, hdr, flags, lcount, list);
   hipLaunchKernelGGL(rfi_spectrum_flags_kernel<TIN>, dim3((unsigned)((g.T + 255) / 256)),
                      dim3(256), 0, s, x, ld, g.C, g.T, g.W, g.J, spart, g.ngroups, fit, lcount,
-                     list, hdr, gflags);
+                     list, hdr, gflags, gspan);
+  hipLaunchKernelGGL(rfi_chunk_bits_kernel, dim3((unsigned)((g.C * g.JW + 255) / 256)), dim3(256), 0,
+                     s, flags, g.C, g.J, g.JW, cbits);
+  hipLaunchKernelGGL(rfi_span_scan_kernel, dim3(1), dim3(1024), 0, s, gspan, g.nspans);
   return hipGetLastError();
 }
 

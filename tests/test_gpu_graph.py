@@ -1,0 +1,95 @@
+"""Captured chunk steps (HIP graphs) replay to the same results as eager
+execution, every replay, with eager work between replays."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1307_5700_amd import synth
+
+from gpu_util import api, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _beam(T):
+    f0, df = synth.band(512)
+    b = synth.Beam(name="graph", nchans=512, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6, ndms=160,
+                   dm_start=0.0, dm_step=0.2, nsamps=T, dtype="u8", seed=71,
+                   bursts=[synth.Burst(c0=50, nch=5, t0=9000, length=2000, amp=20.0)],
+                   spikes=[synth.Spike(t0=21000, length=2, amp=20.0)])
+    s = oracle.delay_table(**b.plan_kwargs())
+    b.pulses = [synth.Pulse(dm_index=100, t0=12000, width=4, amp=1.0)]
+    return b, s
+
+
+def test_single_shot_graph_replays_match_eager():
+    A = api()
+    b, s = _beam(40000)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    T = 8192
+    xbuf = torch.zeros((512, T), dtype=torch.uint8, device="cuda")
+    xbuf.copy_(torch.from_numpy(x[:, :T]))
+    g = A.ChunkGraph(plan, xbuf, rfi=True, nsigma=6.0)
+    for k in range(4):
+        chunk = torch.from_numpy(x[:, k * T:(k + 1) * T]).cuda()
+        xbuf.copy_(chunk)                       # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        st = plan.rfi_threshold(chunk)
+        out, norm, nout, _ = plan.execute(chunk, rfi_state=st)
+        det = plan.detect(out, nout, norm, 6.0)
+        torch.cuda.synchronize()
+        assert torch.equal(g.out[:, :nout], out[:, :nout]), k
+        gc, gn = plan.candidates_to_host(g.det[0], g.det[1])
+        ec, en = plan.candidates_to_host(det[0], det[1])
+        assert gn == en and np.array_equal(gc, ec), k
+
+
+def test_streaming_graph_replays_match_eager_stream():
+    A = api()
+    b, s = _beam(4096 * 9)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    T = 4096
+    assert T > plan.max_delay
+    eager_beam, graph_beam = A.Beam(plan), A.Beam(plan)
+    eager = []
+    for k in range(9):
+        chunk = to_dev(x[:, k * T:(k + 1) * T])
+        out, _, nout, s0 = plan.execute(chunk, rfi_state=plan.rfi_threshold(chunk), beam=eager_beam)
+        eager.append((s0, out[:, :nout].clone()))
+    # the graph's beam runs the first two chunks eagerly, then captures
+    for k in range(2):
+        chunk = to_dev(x[:, k * T:(k + 1) * T])
+        plan.execute(chunk, rfi_state=plan.rfi_threshold(chunk), beam=graph_beam)
+    xbuf = torch.zeros((512, T), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    g = A.ChunkGraph(plan, xbuf, rfi=True, beam=graph_beam)
+    for k in range(2, 9):
+        xbuf.copy_(torch.from_numpy(x[:, k * T:(k + 1) * T]).cuda())
+        torch.cuda.synchronize()
+        s0 = g.replay()
+        torch.cuda.synchronize()
+        assert s0 == eager[k][0], k
+        assert torch.equal(g.out[:, :T], eager[k][1]), k
+    assert graph_beam.position() == eager_beam.position()
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_1307_5700_amd import autotune
+    b, _ = _beam(16384)
+    path = str(tmp_path / "tune.json")
+    r = autotune.best_tiling(b.plan_kwargs(), "u8", True, 16384, path=path)
+    assert 1 <= r["hint"] <= autotune.N_TILINGS
+    times = {int(h): t for h, t in r["all"].items() if t is not None}
+    assert r["ms"] == min(times.values())
+    cached = json.load(open(path))
+    assert len(cached) == 1
+    again = autotune.best_tiling(b.plan_kwargs(), "u8", True, 16384, path=path)
+    assert again == r
