@@ -9,9 +9,25 @@ sigma, thresholds at 5 sigma, detection at 6 sigma.  Inputs are resident in
 HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload paper|batch|serve|precision]
 
 Prints one JSON line.  The metric is dedispersed DM-trial samples per second
-(ndms x outputs per chunk / time per step).
+(ndms x outputs per chunk / time per step).  The default workload is the
+paper-shaped beam above; the others measure the systems patterns on their
+own workloads:
+
+  batch      eight uint8 beams with uneven plans (512-2048 channels, 320-1280
+             DMs, chunks of 16384-131072 samples) as one HIP graph per chunk
+             step around one persistent launch, tiling from the autotuner;
+             beside it the same beams in FP32 one by one, eagerly (the plain
+             single-beam path), and the speedup between the two
+  serve      32 uint8 beams of 1024 channels / 640 DMs fed as Poisson chunk
+             requests (8192-65536 samples) through the continuous-batching
+             server: p50/p99 latency at a paced rate, saturated throughput and
+             the number of beams it sustains in real time
+  precision  4096 channels x 262144 samples x 2048 DMs in FP32, FP16 and
+             uint8 storage: throughput of each and error against the FP64
+             oracle on sampled DM rows
 """
 from __future__ import annotations
 
@@ -36,6 +52,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -114,10 +131,14 @@ def main():
               "(the design notes describe how it would shard by beam, DM or time)", file=sys.stderr)
         sys.exit(2)
     import torch
+    torch.cuda.set_device(0)
+    if args.workload != "paper":
+        res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision}[args.workload](args)
+        print(json.dumps(res), flush=True)
+        return
     from paper_1307_5700_amd import api as A
     from paper_1307_5700_amd import synth
 
-    torch.cuda.set_device(0)
     beam = synth.paper_beam()
     plan = A.Plan.from_beam(beam)
     x_host = synth.render(beam, plan.delays())
@@ -205,6 +226,174 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(beam, x_host, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def _timed(fn, steps: int, warmup: int, stream=None) -> float:
+    """Seconds per call of fn, bracketed by device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _line(metric_value, dt, args, dtype, config, extra):
+    res = {"metric": "DM-trial samples/s", "value": metric_value, "unit": "DM-trial samples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    res.update(extra)
+    return res
+
+
+def bench_batch(args):
+    """Eight uneven uint8 beams: one captured chunk step (RFI passes, one
+    persistent dedispersion launch, detection) against the same beams in
+    FP32 one at a time."""
+    import torch
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import autotune, synth
+    beams = synth.batch_beams("u8")
+    hint = autotune.best_shared_tiling([b.plan_kwargs() for b in beams], "u8", True,
+                                       [b.nsamps for b in beams])
+    plans = [A.Plan.from_beam(b, tile_hint=hint) for b in beams]
+    xs = [torch.from_numpy(synth.render(b, p.delays())).cuda() for b, p in zip(beams, plans)]
+    bms = [A.Beam(p) for p in plans]
+    # one eager chunk fills every ring; the captured step is the steady state
+    A.execute_batch([dict(plan=p, x=x, rfi_state=p.rfi_threshold(x), beam=bm)
+                     for p, x, bm in zip(plans, xs, bms)])
+    torch.cuda.synchronize()
+    g = A.BatchGraph(plans, xs, bms, rfi=True, nsigma=6.0)
+    dt = _timed(g.replay, args.steps, args.warmup)
+    samples = g.dm_trial_samples
+    del g
+
+    # the plain path: FP32 storage, default tiling, one beam after another
+    plain = []
+    for b32 in synth.batch_beams("f32"):
+        p = A.Plan.from_beam(b32)
+        x = torch.from_numpy(synth.render(b32, p.delays())).cuda()
+        bm = A.Beam(p)
+        st = p.rfi_threshold(x)
+        p.execute(x, rfi_state=st, beam=bm)
+        out = p.alloc_output(x.shape[1])
+        norm = p.alloc_norm()
+        det = p.alloc_detect(1 << 15)
+        plain.append((p, x, bm, st, out, norm, det))
+    torch.cuda.synchronize()
+
+    def plain_step():
+        for p, x, bm, st, out, norm, det in plain:
+            p.rfi_threshold(x, st)
+            _, _, nout, s0 = p.execute(x, rfi_state=st, out=out, norm=norm, beam=bm)
+            p.detect(out, nout, norm, 6.0, sample0=s0, buffers=det)
+
+    dt_plain = _timed(plain_step, max(2, args.steps // 4), 1)
+    cfg = {"workload": "batched_multibeam_8beams_u8",
+           "beams": [{"nchans": b.nchans, "ndms": b.ndms, "chunk": b.nsamps} for b in beams],
+           "tiling_hint": hint, "tiling": plans[0].tiling, "graph": True, "rfi": "p=3 W=256 k=5",
+           "parallelism": "none"}
+    return _line(samples / dt, dt, args, "u8", cfg, {
+        "plain_f32_single_beam": {"value": samples / dt_plain, "ms_per_step": dt_plain * 1e3,
+                                  "path": "FP32 storage, default tiling, eager, one beam at a time"},
+        "speedup_vs_plain_f32": dt_plain / dt})
+
+
+def bench_serve(args):
+    """32 uint8 beams through the continuous-batching server."""
+    import torch
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import serve, synth
+    beams = synth.served_beams(32)
+    plan = A.Plan.from_beam(beams[0])
+    rng = np.random.default_rng(7)
+    # a pool of distinct uint8 noise blocks; each request takes a slice
+    pool = [synth.quantise(synth.noise((plan.nchans, 65536), seed=900 + k), "u8") for k in range(4)]
+    lengths = np.arange(8192, 65536 + 1, 1024)
+
+    def chunks(n_per_beam):
+        out = {}
+        for i in range(len(beams)):
+            lst = []
+            for _ in range(n_per_beam):
+                L = int(rng.choice(lengths))
+                blk = pool[int(rng.integers(0, len(pool)))]
+                a = int(rng.integers(0, 65536 - L + 1)) // 4 * 4
+                lst.append(blk[:, a:a + L])          # a view: no host copy
+            out[i] = lst
+        return out
+
+    budget = int(torch.cuda.get_device_properties(0).total_memory * 0.5)
+    results = {}
+    for label, speedup, n_per_beam in (("paced", 16.0, 6), ("saturated", 1e9, 4)):
+        srv = serve.Server(plan, max_chunk=65536, hbm_budget=budget, nsigma=6.0, max_slots=16,
+                           nstreams=4)
+        for i in range(len(beams)):
+            srv.add_beam(i)
+        # warm-up: one short chunk per beam fills the rings
+        for i in range(len(beams)):
+            srv.submit(serve.Request(beam_id=i, data=pool[0][:, :8192],
+                                     t_arrival=time.perf_counter()))
+        srv.drain()
+        srv.done.clear()
+        r = serve.poisson_run(srv, chunks(n_per_beam), beams[0].tsamp_s, speedup, seed=11)
+        results[label] = r
+        del srv
+        torch.cuda.synchronize()
+    sat = results["saturated"]
+    rt_rate = plan.ndms / beams[0].tsamp_s          # DM-trial samples/s of one real-time beam
+    cfg = {"workload": "served_stream_32beams_1024ch_640dm_u8", "chunks": "8192-65536 (Poisson)",
+           "hbm_budget_bytes": budget, "parallelism": "none"}
+    dt = sat["wall_s"] / max(sat["chunks"], 1)
+    return _line(sat["dm_trial_samples_per_s"], dt, args, "u8", cfg, {
+        "latency_paced": {k: results["paced"][k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "n",
+                                                           "speedup", "launches", "chunks")},
+        "latency_saturated": {k: sat[k] for k in ("p50_ms", "p99_ms", "n", "launches", "chunks")},
+        "sustained_realtime_beams": sat["dm_trial_samples_per_s"] / rt_rate})
+
+
+def bench_precision(args):
+    """The 4096-channel plane in three storage types; error on sampled rows."""
+    import torch
+    import oracle
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    base = synth.precision_beam("f32")
+    plan32 = A.Plan.from_beam(base)
+    s = plan32.delays()
+    x32 = synth.render(base, s)
+    T = x32.shape[1]
+    nout = T - plan32.max_delay
+    rows = np.unique(np.concatenate([[0, plan32.ndms - 1], [p.dm_index for p in base.pulses[:6]]]))
+    per = {}
+    for dt_name in ("f32", "f16", "u8"):
+        beam = synth.precision_beam(dt_name)
+        xh = x32 if dt_name == "f32" else synth.quantise(x32, dt_name)
+        plan = A.Plan.from_beam(beam)
+        x = torch.from_numpy(xh).cuda()
+        out = plan.alloc_output(nout)
+        norm = plan.alloc_norm()
+
+        def step():
+            plan.execute(x, out=out, norm=norm)
+        dt = _timed(step, max(2, args.steps // 4), 1)
+        D = out[:, :nout][torch.from_numpy(rows).cuda()].cpu().numpy()
+        ref = oracle.dedisperse_rows(xh, s, rows, nout)
+        scale = np.maximum(np.abs(ref), ref.std(axis=1, keepdims=True))
+        err = float(np.max(np.abs(D.astype(np.float64) - ref) / scale))
+        per[dt_name] = {"ms": dt * 1e3, "value": plan.ndms * nout / dt, "err_vs_fp64_oracle": err}
+        del x, out
+        torch.cuda.empty_cache()
+    for k in per:
+        per[k]["speedup_vs_f32"] = per["f32"]["ms"] / per[k]["ms"]
+    cfg = {"workload": "precision_sweep_4096ch_262144samp_2048dm", "rows_checked": rows.tolist(),
+           "parallelism": "none"}
+    best = min(per, key=lambda k: per[k]["ms"])
+    return _line(per[best]["value"], per[best]["ms"] * 1e-3, args, best, cfg, {"storage": per})
 
 
 def _kernel_hash() -> str:

@@ -92,6 +92,8 @@ typedef struct {
   int32_t dm_block;     /* DMs per dedispersion workgroup (tiling info)   */
   int32_t time_tile;    /* output samples per dedispersion workgroup      */
   int32_t chan_block;   /* channels per LDS stage                         */
+  int32_t tile_index;   /* 1-based index of the compiled tiling in use    */
+  int32_t waves;        /* wave64s per dedispersion workgroup             */
   int64_t lds_bytes;    /* LDS per dedispersion workgroup                 */
 } mb_plan_info;
 
@@ -171,6 +173,9 @@ mb_status dedisp_plan_destroy(mb_plan* plan);
 mb_status dedisp_plan_info(const mb_plan* plan, mb_plan_info* info);
 /* Copies the delay table, int32 [ndms][nchans] row-major, to host memory. */
 mb_status dedisp_plan_delays(const mb_plan* plan, int32_t* h_delays);
+/* Number of compiled dedispersion tilings; valid tile_hint values are
+ * 1..count.  Host only, no device call.  EINVAL if count is NULL. */
+mb_status dedisp_tilings(int32_t* count);
 
 /* ---- RFI thresholding (Sec. 2.2.1) ------------------------------------ */
 

@@ -36,7 +36,8 @@ class PlanDesc(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("nchans", c_i32), ("ndms", c_i32), ("max_delay", c_i32), ("dm_block", c_i32),
-                ("time_tile", c_i32), ("chan_block", c_i32), ("lds_bytes", c_i64)]
+                ("time_tile", c_i32), ("chan_block", c_i32), ("tile_index", c_i32), ("waves", c_i32),
+                ("lds_bytes", c_i64)]
 
 
 class RfiReport(ctypes.Structure):
@@ -70,6 +71,7 @@ _SIGS = {
     "dedisp_plan_destroy": ([c_vp], c_i32),
     "dedisp_plan_info": ([c_vp, ctypes.POINTER(PlanInfo)], c_i32),
     "dedisp_plan_delays": ([c_vp, c_vp], c_i32),
+    "dedisp_tilings": ([ctypes.POINTER(c_i32)], c_i32),
     "mb_rfi_defaults": ([ctypes.POINTER(RfiParams)], None),
     "rfi_state_layout": ([c_vp, c_i64, ctypes.POINTER(RfiLayout)], c_i32),
     "rfi_threshold": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp], c_i32),

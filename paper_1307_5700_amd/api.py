@@ -76,8 +76,9 @@ class Plan:
         L.check(L.lib().dedisp_plan_info(h, ctypes.byref(info)), "dedisp_plan_info")
         self.nchans, self.ndms = info.nchans, info.ndms
         self.max_delay = info.max_delay
-        self.tiling = dict(dm_block=info.dm_block, time_tile=info.time_tile,
-                           chan_block=info.chan_block, lds_bytes=info.lds_bytes)
+        self.tiling = dict(index=info.tile_index, waves=info.waves, dm_block=info.dm_block,
+                           time_tile=info.time_tile, chan_block=info.chan_block,
+                           lds_bytes=info.lds_bytes)
         self.dm_start, self.dm_step = float(dm_start), float(dm_step)
         ws = ctypes.c_size_t()
         L.check(L.lib().detect_workspace_size(h, ctypes.byref(ws)), "detect_workspace_size")
@@ -225,6 +226,13 @@ class Plan:
         return peaks.cpu().numpy().view(PEAK_DTYPE)
 
 
+def num_tilings() -> int:
+    """Number of compiled dedispersion tilings (valid tile_hint: 1..n)."""
+    n = ctypes.c_int32()
+    L.check(L.lib().dedisp_tilings(ctypes.byref(n)), "dedisp_tilings")
+    return n.value
+
+
 def alloc_batch_work(nitems: int, device=None) -> torch.Tensor:
     n = ctypes.c_size_t()
     L.check(L.lib().dedisp_batch_workspace_size(int(nitems), ctypes.byref(n)), "dedisp_batch_workspace_size")
@@ -358,3 +366,68 @@ class ChunkGraph:
         self._first = False
         self.graph.replay()
         return self.sample0
+
+
+class BatchGraph:
+    """The chunk step of several beams captured as one HIP graph.
+
+    Per beam the RFI pass, then one batched persistent dedispersion launch
+    over every beam (with normalisation), then per beam detection.  All plans
+    must share the storage type and the tiling.  Capture once every beam is
+    in steady state (its ring is full); each replay then processes the
+    current contents of ``xs`` as the next chunk of every beam.
+    """
+
+    def __init__(self, plans, xs, beams, rfi: bool = True, nsigma: float = 6.0,
+                 capacity: int = 1 << 15):
+        if not (len(plans) == len(xs) == len(beams)) or not plans:
+            raise ValueError("one plan, input and beam per item")
+        self.plans, self.xs, self.beams, self.nsigma = list(plans), list(xs), list(beams), float(nsigma)
+        self.T = []
+        for p, x, b in zip(plans, xs, beams):
+            T, _ = p._check_input(x)
+            if T % 4 or b.position() < ((p.max_delay + 3) // 4) * 4:
+                raise ValueError("capture beams in steady state with chunk lengths multiple of 4")
+            self.T.append(T)
+        dev = plans[0].device
+        self.states = [p.alloc_rfi_state(T) if rfi else None for p, T in zip(plans, self.T)]
+        self.outs = [p.alloc_output(T) for p, T in zip(plans, self.T)]
+        self.norms = [p.alloc_norm() for p in plans]
+        self.dets = [p.alloc_detect(capacity) for p in plans]
+        self.work = alloc_batch_work(len(plans), dev)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.graph = torch.cuda.CUDAGraph()
+        self.sample0 = None
+        self._first = True
+        torch.cuda.synchronize(dev)
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self._enqueue()
+
+    def _enqueue(self):
+        for p, x, st in zip(self.plans, self.xs, self.states):
+            if st is not None:
+                p.rfi_threshold(x, st)
+        jobs = [dict(plan=p, x=x, rfi_state=st, out=o, norm=n, beam=b)
+                for p, x, st, o, n, b in zip(self.plans, self.xs, self.states, self.outs,
+                                             self.norms, self.beams)]
+        res = execute_batch(jobs, work=self.work)
+        s0s = []
+        for p, (out, norm, nout, s0), det in zip(self.plans, res, self.dets):
+            p.detect(out, nout, norm, self.nsigma, sample0=s0, buffers=det)
+            s0s.append(s0)
+        self.sample0 = s0s
+
+    @property
+    def dm_trial_samples(self) -> int:
+        """Dedispersed samples one replay produces over all beams."""
+        return sum(p.ndms * T for p, T in zip(self.plans, self.T))
+
+    def replay(self):
+        """Runs the captured step; returns each beam's first output sample."""
+        if not self._first:
+            for b, T in zip(self.beams, self.T):
+                b.advance(T)
+            self.sample0 = [s + T for s, T in zip(self.sample0, self.T)]
+        self._first = False
+        self.graph.replay()
+        return list(self.sample0)

@@ -16,7 +16,6 @@ import torch
 
 from . import api as A
 
-N_TILINGS = 6
 
 
 def cache_path() -> str:
@@ -40,8 +39,19 @@ def _load(path):
         return {}
 
 
+def _synthetic_chunk(nchans: int, nsamps: int, dtype: str, device, seed: int) -> torch.Tensor:
+    """N(0,1) noise in the storage type, generated on the device."""
+    g = torch.Generator(device=device).manual_seed(seed)
+    v = torch.randn((nchans, nsamps), generator=g, device=device)
+    if dtype == "f16":
+        return v.half()
+    if dtype == "u8":
+        return (128 + 16 * v).round_().clamp_(0, 255).to(torch.uint8)
+    return v
+
+
 def time_tiling(plan_kwargs: dict, dtype: str, rfi: bool, nsamps: int, hint: int,
-                reps: int = 5, seed: int = 123) -> float | None:
+                reps: int = 5, seed: int = 123, x: torch.Tensor | None = None) -> float | None:
     """Milliseconds of one dedispersion launch with tiling ``hint``; None
     when the tiling does not fit the plan."""
     try:
@@ -50,10 +60,8 @@ def time_tiling(plan_kwargs: dict, dtype: str, rfi: bool, nsamps: int, hint: int
         return None
     if nsamps <= plan.max_delay:
         raise ValueError("chunk shorter than the largest delay")
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    v = torch.randn((plan.nchans, nsamps), generator=g)
-    x = {"f32": v, "f16": v.half(), "u8": (128 + 16 * v).round().clamp(0, 255).to(torch.uint8)}[dtype]
-    x = x.to(plan.device)
+    if x is None:
+        x = _synthetic_chunk(plan.nchans, nsamps, dtype, plan.device, seed)
     st = plan.rfi_threshold(x) if rfi else None
     out = plan.alloc_output(nsamps - plan.max_delay)
     for _ in range(2):
@@ -65,6 +73,7 @@ def time_tiling(plan_kwargs: dict, dtype: str, rfi: bool, nsamps: int, hint: int
         plan.execute(x, rfi_state=st, out=out, norm=False)
     e1.record()
     torch.cuda.synchronize()
+    plan.close()
     return e0.elapsed_time(e1) / reps
 
 
@@ -76,7 +85,10 @@ def best_tiling(plan_kwargs: dict, dtype: str = "f32", rfi: bool = True, nsamps:
     cache = _load(path)
     if key in cache and not retune:
         return cache[key]
-    times = {h: time_tiling(plan_kwargs, dtype, rfi, nsamps, h) for h in range(1, N_TILINGS + 1)}
+    dev = torch.device("cuda", torch.cuda.current_device())
+    x = _synthetic_chunk(int(plan_kwargs["nchans"]), nsamps, dtype, dev, 123)
+    times = {h: time_tiling(plan_kwargs, dtype, rfi, nsamps, h, x=x) for h in range(1, A.num_tilings() + 1)}
+    del x
     ok = {h: t for h, t in times.items() if t is not None}
     if not ok:
         raise RuntimeError("no compiled tiling fits this plan")

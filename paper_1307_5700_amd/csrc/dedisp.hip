@@ -62,27 +62,24 @@ template <> struct Quad<uint8_t> {
   static __device__ inline float one(const uint8_t* p) { return (float)*p; }
 };
 
-// One aligned quad of virtual samples in flight.
-enum : uint32_t { kReady = 0, kChunk = 1 };
-
-template <typename TIN> struct Staged {
-  float4 v;                          // ring / tail values (and f32 chunk values)
-  typename Quad<TIN>::Raw raw;       // u8 / f16 chunk values
-  uint32_t meta;                     // kind; chunk sample index t << 1 for chunk quads
+// One aligned quad of virtual samples in flight.  Every quad is one vector
+// load from an address that is always in bounds, with no branch around it:
+// divergent load paths that write the same registers make the compiler wait
+// for every outstanding load at their join, which would serialise the
+// prefetch of the next channel block with the accumulation of this one.
+// Which samples of the quad are valid, whether it comes from the ring, and
+// the cleaning are all applied with selects when the quad is written to LDS.
+template <typename TIN, bool RING> struct Staged {
+  typename Quad<TIN>::Raw raw;       // chunk values (f32: chunk or ring values)
+  float4 rv;                         // ring values (u8 / f16 with a ring only)
+  int32_t t;                         // chunk index of the first sample: < 0 ring,
+                                     // >= L (or kNoQuad) nothing to stage
 };
+constexpr int32_t kNoQuad = 0x3fffffff;
 
 // Chunk index of chunk sample t (W is a power of two).
 __device__ inline uint32_t chunk_of(const CleanView& cv, int64_t t) {
   return (uint32_t)t >> cv.wshift;
-}
-
-template <typename TIN, bool CLEAN>
-__device__ inline float clean_one(const DedispArgs& A, const TIN* xrow, int64_t c, float fit,
-                                  int64_t t) {
-  const float v = Quad<TIN>::one(xrow + t);
-  if (!CLEAN) return v;
-  const bool f = (A.clean.cflags[c * A.clean.J + chunk_of(A.clean, t)] & 2) || A.clean.gflags[t];
-  return f ? 0.0f : v - fit;
 }
 
 // Row of one staged channel: where its window starts and, for cleaning, the
@@ -94,73 +91,112 @@ struct RowMeta {
   int32_t g_lo, g_hi;   // prefix counts of flagged spectra bracketing the window
 };
 
-// Issues the loads of the quad at virtual index tau (a multiple of 4).
-template <typename TIN, bool CLEAN, bool RING>
-__device__ inline void issue(Staged<TIN>& s, const DedispArgs& A, const TIN* xrow,
-                             const float* ringrow, int64_t c, float fit, int64_t tau, int64_t V,
-                             int64_t p0) {
+// Issues the load of the quad at virtual index tau (a multiple of 4); `live`
+// is false for lanes past the end of their range.  Rows are ld >= L apart
+// with ld a multiple of 4, so the aligned quad holding any chunk sample lies
+// inside its row.
+template <typename TIN, bool RING>
+__device__ inline void issue(Staged<TIN, RING>& s, const DedispArgs& A, const TIN* xrow,
+                             const float* ringrow, int64_t tau, bool live, int64_t p0) {
   const int64_t v = RING ? A.ring_valid : 0;
-  if (tau >= v && tau + 3 < V) {
-    const int64_t t = tau - v;
-    if constexpr (std::is_same<TIN, float>::value) s.v = Quad<TIN>::load(xrow + t);
-    else s.raw = Quad<TIN>::load(xrow + t);
-    s.meta = kChunk | ((uint32_t)t << 1);
-  } else if (RING && tau < v) {
+  const int64_t t = tau - v;
+  const bool in_chunk = live && t >= 0 && t < A.L;
+  const TIN* px = xrow + (in_chunk ? t : 0);
+  if constexpr (RING) {
+    const bool in_ring = live && tau < v;
     int64_t p = p0 + tau;
     if (p >= A.R) p -= A.R;
-    s.v = *reinterpret_cast<const float4*>(ringrow + p);
-    s.meta = kReady;
-  } else {
-    float e[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t ti = tau + i;
-      e[i] = (ti < V) ? clean_one<TIN, CLEAN>(A, xrow, c, fit, ti - v) : 0.0f;
+    if constexpr (std::is_same<TIN, float>::value) {
+      const float* pr = in_ring ? ringrow + p : px;
+      s.raw = *reinterpret_cast<const float4*>(pr);
+    } else {
+      s.raw = Quad<TIN>::load(px);
+      if (A.ring_valid > 0)        // uniform: the ring exists
+        s.rv = *reinterpret_cast<const float4*>(ringrow + (in_ring ? p : 0));
+      else
+        s.rv = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    s.v = make_float4(e[0], e[1], e[2], e[3]);
-    s.meta = kReady;
+    s.t = !live ? kNoQuad : (in_ring ? -1 : (int32_t)min(t, (int64_t)kNoQuad));
+  } else {
+    s.raw = Quad<TIN>::load(px);
+    s.t = (live && t < A.L) ? (int32_t)t : kNoQuad;
   }
 }
 
-// Widens and cleans a landed quad.  Chunk flags come from the row's 64-bit
-// mask; spectrum flags are read per quad only when the window holds any.
-template <typename TIN, bool CLEAN>
-__device__ inline float4 finish(const Staged<TIN>& s, const DedispArgs& A, const RowMeta& rm,
+// Widens and cleans a landed quad: samples past the chunk end are 0; ring
+// samples were cleaned when they entered the ring.  Chunk flags come from
+// the row's 64-bit mask; spectrum flags are read per quad only when the
+// window holds any.
+template <typename TIN, bool CLEAN, bool RING>
+__device__ inline float4 finish(const Staged<TIN, RING>& s, const DedispArgs& A, const RowMeta& rm,
                                 bool any_g, float fit) {
-  if ((s.meta & 1) == kReady) return s.v;
   float4 f;
-  if constexpr (std::is_same<TIN, float>::value) f = s.v;
+  if constexpr (std::is_same<TIN, float>::value) f = s.raw;
   else f = Quad<TIN>::widen(s.raw);
+  const int32_t t = s.t;
+  const bool ring = RING && t < 0;
+  const int32_t tc = (t < 0 || t >= A.L) ? 0 : t;           // in-range stand-in for addressing
+  bool z0 = t + 0 >= A.L, z1 = t + 1 >= A.L, z2 = t + 2 >= A.L, z3 = t + 3 >= A.L;
+  float sub = 0.0f;
   if (CLEAN) {
-    const uint32_t t = s.meta >> 1;
-    const int jr = (int)chunk_of(A.clean, t) - rm.j0;          // 0..63
+    const int jr = (int)chunk_of(A.clean, tc) - rm.j0;       // 0..63 inside the window
     const uint32_t word = jr < 32 ? rm.m_lo : rm.m_hi;
-    const bool cf = (word >> (jr & 31)) & 1u;
+    const bool cf = ((word >> (jr & 31)) & 1u) != 0;
     uint32_t g = 0;
-    if (any_g) g = *reinterpret_cast<const uint32_t*>(A.clean.gflags + t);
-    f.x = (cf || (g & 0xffu)) ? 0.0f : f.x - fit;
-    f.y = (cf || (g & 0xff00u)) ? 0.0f : f.y - fit;
-    f.z = (cf || (g & 0xff0000u)) ? 0.0f : f.z - fit;
-    f.w = (cf || (g & 0xff000000u)) ? 0.0f : f.w - fit;
+    if (any_g) g = *reinterpret_cast<const uint32_t*>(A.clean.gflags + tc);
+    z0 = z0 || cf || (g & 0xffu); z1 = z1 || cf || (g & 0xff00u);
+    z2 = z2 || cf || (g & 0xff0000u); z3 = z3 || cf || (g & 0xff000000u);
+    sub = fit;
   }
-  return f;
+  float4 r;
+  r.x = z0 ? 0.0f : f.x - sub;
+  r.y = z1 ? 0.0f : f.y - sub;
+  r.z = z2 ? 0.0f : f.z - sub;
+  r.w = z3 ? 0.0f : f.w - sub;
+  if constexpr (RING) {
+    if constexpr (std::is_same<TIN, float>::value) {
+      if (ring) r = f;
+    } else {
+      if (ring) r = s.rv;
+    }
+  }
+  return r;
+}
+
+// The G per-DM LDS offsets of one wave for one staged channel (int2 or
+// int4 broadcast reads).
+template <int G>
+__device__ inline void load_offsets(const int* src, int (&o)[G]) {
+  if constexpr (G == 2) {
+    const int2 o2 = *reinterpret_cast<const int2*>(src);
+    o[0] = o2.x; o[1] = o2.y;
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; g += 4) {
+      const int4 o4 = *reinterpret_cast<const int4*>(src + g);
+      o[g] = o4.x; o[g + 1] = o4.y; o[g + 2] = o4.z; o[g + 3] = o4.w;
+    }
+  }
 }
 
 // One (DM block, time tile) of one launch item; all threads of the
 // workgroup call it.  lds: the dynamic LDS of the workgroup.
-template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC>
+template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
 __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* __restrict__ relb,
                                             const float* __restrict__ fit32, float* lds,
                                             int dblock, int ttile) {
   constexpr int NT = 64 * NW, BD = NW * G, BT = 256 * Q;
-  // staging: NW >= BC: WPR waves share a row, each loads all of it and writes
-  // CPW of its 4 copies; NW < BC: each wave stages RPW whole rows
+  // staging: NW >= BC: WPR waves share a row and split its quads (each a
+  // contiguous range, one quad of overlap); NW < BC: each wave stages RPW
+  // whole rows.  KM quads per lane and row cover rows of up to
+  // 64*kStageQuads quads.
   constexpr int WPR = NW >= BC ? NW / BC : 1;
   constexpr int RPW = NW >= BC ? 1 : BC / NW;
-  constexpr int CPW = 4 / WPR;
-  constexpr int KM = kStageQuads / RPW;
-  static_assert(G % 4 == 0 && WPR * CPW == 4 && (NW >= BC ? NW % BC == 0 : BC % NW == 0) &&
-                RPW * KM == kStageQuads && BD * BC <= NT, "tiling");
+  constexpr int QWMAX = (64 * kStageQuads - 1 + WPR - 1) / WPR + 1;
+  constexpr int KM = RPW > 1 ? kStageQuads / RPW : (QWMAX + 63) / 64;
+  static_assert((G == 2 || G % 4 == 0) && (NW >= BC ? NW % BC == 0 : BC % NW == 0) &&
+                (RPW == 1 || RPW * KM == kStageQuads) && BD * BC <= NT && kAccGroup % BC == 0,
+                "tiling");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -172,7 +208,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   const int RS = A.rs;
   const int RS4 = RS >> 2;
   const int64_t vring = RING ? A.ring_valid : 0;
-  const int64_t V = vring + A.L;
   // ring position of virtual sample 0: from the beam's device-side sample
   // count when given (so a captured launch stays right on replay)
   int64_t p0 = A.ring_p0;
@@ -181,13 +216,26 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     p0 = (sn - vring) % A.R;
   }
   const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;   // DM d0's delays
-  int* lds_off = reinterpret_cast<int*>(lds + BC * 4 * RS);      // [BC][BD]
+  // LDS: one stage (or two, double-buffered) of BC rows x 4 copies x RS
+  // samples followed by the stage's [BC][BD] window offsets
+  constexpr bool DB = (P & 2) != 0;
+  const int stage_floats = BC * 4 * RS + BC * BD;
+  auto stage_rows = [&](int b) { return lds + b * stage_floats; };
+  auto stage_off = [&](int b) { return reinterpret_cast<int*>(lds + b * stage_floats + BC * 4 * RS); };
 
   auto row_of = [&](int rr) { return NW >= BC ? wave / WPR : wave + NW * rr; };
+  // this wave's quads of its row(s): [m0, mend); the last quad of a range
+  // that is not the row's last is written by the next wave as well, which
+  // alone has its successor quad and so writes its shifted copies
+  const int wr = NW >= BC ? wave % WPR : 0;
+  const int qw = WPR > 1 ? (RS4 - 1 + WPR - 1) / WPR + 1 : RS4;
+  const int m0 = wr * (qw - 1);
+  const int mend = min(m0 + qw, RS4);
 
-  Staged<TIN> st[RPW][KM];
+  Staged<TIN, RING> st[RPW][KM];
   RowMeta rm[RPW];
   int basen[RPW];        // s[d0][c] of the row in the block after next (vector load, lands early)
+  float fitn[RPW];       // bandpass value of the row being staged (loaded with its quads)
   int offreg = 0;
 
   // Cleaning metadata of row c (vector loads: they count on vmcnt only, so
@@ -220,22 +268,24 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         const int64_t a = t0 + (base & ~3);
         const TIN* xrow = static_cast<const TIN*>(A.x) + (int64_t)c * A.ld;
         const float* ringrow = RING ? A.ring + (int64_t)c * A.R : nullptr;
-        const float fit = CLEAN ? fit32[c + lane * A.zero] : 0.0f;
         load_meta(rm[rr], c, a);
+        if (CLEAN) fitn[rr] = fit32[c + lane * A.zero];
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-          const int m = lane + 64 * k;
-          if (m < RS4) issue<TIN, CLEAN, RING>(st[rr][k], A, xrow, ringrow, c, fit, a + 4 * m, V, p0);
-          else { st[rr][k].v = make_float4(0.f, 0.f, 0.f, 0.f); st[rr][k].meta = kReady; }
+          const int m = m0 + lane + 64 * k;
+          issue<TIN, RING>(st[rr][k], A, xrow, ringrow, a + 4 * m, m < mend, p0);
         }
       }
       const int cn = cb0 + BC + row_of(rr);
       if (cn < C) basen[rr] = dl[cn + lane * A.zero];
     }
-    if (tid < BD * BC) {
-      const int dd = tid % BD, cb = tid / BD;
+    {
+      // unconditional load from a clamped index (no load inside a divergent
+      // branch, see Staged); rows past C get offset 0 when it is written
+      const int dd = tid % BD, cb = min(tid / BD, BC - 1);
       const int d = min(d0 + dd, dlast);
-      offreg = (cb0 + cb < C) ? relb[(int64_t)d * A.relb_ld + cb0 + cb] : 0;
+      const int cc = min(cb0 + cb, C - 1);
+      offreg = relb[(int64_t)d * A.relb_ld + cc];
     }
   };
 
@@ -243,18 +293,25 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // lane's quad is the next lane's (a DPP wave shift); lane 63 takes lane 0's
   // quad of the next k.  The last quad of a row has no successor in
   // registers, but no DM window reads the copy positions it would feed.
-  auto write_block = [&](int cb0) {
+  auto write_block = [&](int cb0, int buf) {
+    float* const rows = stage_rows(buf);
+    int* const lds_off = stage_off(buf);
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       const int cb = row_of(rr);
       const int c = cb0 + cb;
-      if (c < C) {
-        const float fit = CLEAN ? fit32[c] : 0.0f;
+      float* row = rows + cb * 4 * RS;
+      if (c >= C) {
+        // rows past the last channel read as zeros (offset 0 of copy 0), so
+        // the accumulation of a block needs no per-channel bound test
+        for (int m = m0 + lane; m < mend; m += 64)
+          *reinterpret_cast<float4*>(row + 4 * m) = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const float fit = CLEAN ? fitn[rr] : 0.0f;
         const bool any_g = CLEAN && (__builtin_amdgcn_readfirstlane(rm[rr].g_hi - rm[rr].g_lo) != 0);
-        float* row = lds + cb * 4 * RS;
         float4 lo[KM];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN>(st[rr][k], A, rm[rr], any_g, fit);
+        for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], any_g, fit);
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           float4 hi;
@@ -268,25 +325,22 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
             const float az = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nx.z), 0));
             if (lane == 63) { hi.x = ax; hi.y = ay; hi.z = az; }
           }
-          const int m = lane + 64 * k;
-          if (m < RS4) {
+          const int m = m0 + lane + 64 * k;
+          if (m < mend) {
             const float4 l = lo[k];
-            // copy r holds the window shifted by r samples; with WPR waves per
-            // row, wave (wave % WPR) writes copies [CPW*(wave % WPR), +CPW)
-            const int wr = NW >= BC ? wave % WPR : 0;
+            // copy r holds the window shifted by r samples
             float* p = row + 4 * m;
-            if (CPW == 4 || wr == 0) *reinterpret_cast<float4*>(p) = l;
-            if (CPW == 4 || (CPW == 2 && wr == 0) || (CPW == 1 && wr == 1))
+            *reinterpret_cast<float4*>(p) = l;
+            if (WPR == 1 || m + 1 < mend || wr == WPR - 1) {
               *reinterpret_cast<float4*>(p + RS) = make_float4(l.y, l.z, l.w, hi.x);
-            if (CPW == 4 || (CPW == 2 && wr == 1) || (CPW == 1 && wr == 2))
               *reinterpret_cast<float4*>(p + 2 * RS) = make_float4(l.z, l.w, hi.x, hi.y);
-            if (CPW == 4 || (CPW == 2 && wr == 1) || (CPW == 1 && wr == 3))
               *reinterpret_cast<float4*>(p + 3 * RS) = make_float4(l.w, hi.x, hi.y, hi.z);
+            }
           }
         }
       }
     }
-    if (tid < BD * BC) lds_off[tid] = offreg;       // [cb][dd] with dd fastest
+    if (tid < BD * BC) lds_off[tid] = (cb0 + tid / BD < C) ? offreg : 0;   // [cb][dd], dd fastest
   };
 
   float4 acc[G][Q], tot[G][Q];
@@ -303,24 +357,38 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     const int c = row_of(rr);
     basen[rr] = c < C ? dl[c] : 0;
   }
+  // Single buffer: per block, issue the loads of block k+1, accumulate block
+  // k, barrier, write block k+1, barrier.  Double buffer: block k+1 is
+  // written into the other stage while block k is accumulated (its loads
+  // were issued one block earlier), then the loads of block k+2 are issued;
+  // one barrier per block.
   issue_block(0);
-  write_block(0);
+  write_block(0, 0);
+  if (DB && BC < C) issue_block(BC);
   __syncthreads();
+  int cur = 0;
   for (int cb0 = 0; cb0 < C; cb0 += BC) {
     const int next = cb0 + BC;
-    if (next < C) issue_block(next);
+    if constexpr (DB) {
+      if (next < C) {
+        write_block(next, cur ^ 1);
+        if (next + BC < C) issue_block(next + BC);
+      }
+    } else {
+      if (next < C) issue_block(next);
+    }
     // ---- accumulate channel block cb0 ----
+    // Straight-line over the BC channels (rows past C are zeros).
+    const char* base = reinterpret_cast<const char*>(stage_rows(cur)) + 16 * lane;
+    const int* lds_off = stage_off(cur);
+    if constexpr ((P & 1) == 0) {
+      // serial: per channel the offsets, then its G*Q reads, then the adds;
+      // latency is hidden by the other resident waves
 #pragma unroll
-    for (int cb = 0; cb < BC; ++cb) {
-      const int c = cb0 + cb;
-      if (c < C) {
-        const char* rowb = reinterpret_cast<const char*>(lds + cb * 4 * RS) + 16 * lane;
+      for (int cb = 0; cb < BC; ++cb) {
+        const char* rowb = base + cb * 16 * RS;
         int off[G];
-#pragma unroll
-        for (int g = 0; g < G; g += 4) {
-          const int4 o4 = *reinterpret_cast<const int4*>(lds_off + cb * BD + wave * G + g);
-          off[g] = o4.x; off[g + 1] = o4.y; off[g + 2] = o4.z; off[g + 3] = o4.w;
-        }
+        load_offsets(lds_off + cb * BD + wave * G, off);
         float4 v[G][Q];
 #pragma unroll
         for (int g = 0; g < G; ++g)
@@ -333,21 +401,57 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
             acc[g][q].x += v[g][q].x; acc[g][q].y += v[g][q].y;
             acc[g][q].z += v[g][q].z; acc[g][q].w += v[g][q].w;
           }
-        if (((c + 1) & (kAccGroup - 1)) == 0) {
+      }
+    } else {
+      // rolling: the block's offsets first (uniform: SGPRs), then per DM
+      // group g the adds of channel cb are followed at once by the reads of
+      // channel cb+1 into the same registers, so up to G*Q reads stay in
+      // flight with no second set of registers
+      int off[BC][G];
 #pragma unroll
-          for (int g = 0; g < G; ++g)
+      for (int cb = 0; cb < BC; ++cb) {
+        load_offsets(lds_off + cb * BD + wave * G, off[cb]);
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-              tot[g][q].x += acc[g][q].x; tot[g][q].y += acc[g][q].y;
-              tot[g][q].z += acc[g][q].z; tot[g][q].w += acc[g][q].w;
-              acc[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        for (int g = 0; g < G; ++g) off[cb][g] = __builtin_amdgcn_readfirstlane(off[cb][g]);
+      }
+      float4 v[G][Q];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[g][q] = reinterpret_cast<const float4*>(base + off[0][g])[64 * q];
+#pragma unroll
+      for (int cb = 0; cb < BC; ++cb) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            acc[g][q].x += v[g][q].x; acc[g][q].y += v[g][q].y;
+            acc[g][q].z += v[g][q].z; acc[g][q].w += v[g][q].w;
+          }
+          if (cb + 1 < BC) {
+            const char* rowb = base + (cb + 1) * 16 * RS;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[g][q] = reinterpret_cast<const float4*>(rowb + off[cb + 1][g])[64 * q];
+          }
         }
       }
     }
+    // partial sums close at every kAccGroup-th channel (BC divides kAccGroup)
+    if (((cb0 + BC) & (kAccGroup - 1)) == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          tot[g][q].x += acc[g][q].x; tot[g][q].y += acc[g][q].y;
+          tot[g][q].z += acc[g][q].z; tot[g][q].w += acc[g][q].w;
+          acc[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
     __syncthreads();
-    if (next < C) {
-      write_block(next);
+    if constexpr (DB) {
+      cur ^= 1;
+    } else if (next < C) {
+      write_block(next, 0);
       __syncthreads();
     }
   }
@@ -381,7 +485,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   }
 }
 
-template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC>
+template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
 __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int32_t* __restrict__ relb,
                                                          const float* __restrict__ fit32) {
   extern __shared__ float4 lds4[];
@@ -393,7 +497,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
   const int xcd = bid & 7, slot = bid >> 3;
   const int q8 = ntile >> 3, rem = ntile & 7;
   const int tile = xcd * q8 + min(xcd, rem) + slot;
-  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC>(A, relb, fit32, reinterpret_cast<float*>(lds4),
+  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P>(A, relb, fit32, reinterpret_cast<float*>(lds4),
                                               tile % A.n_dblocks, tile / A.n_dblocks);
 }
 
@@ -401,7 +505,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
 // one tiling).  Workgroups take tiles from an atomic counter in item order,
 // heaviest items first, until the counter passes the total; every
 // workgroup reaches that exit.
-template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC>
+template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC, int P>
 __global__ __launch_bounds__(64 * NW) void dedisp_batch_kernel(BatchArgs B) {
   extern __shared__ float4 lds4[];
   __shared__ int tile_sh;
@@ -415,7 +519,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_batch_kernel(BatchArgs B) {
     while (i + 1 < B.nitems && t >= B.item[i + 1].tile0) ++i;
     const BatchItem& it = B.item[i];
     const int local = t - it.tile0;
-    dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
+    dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC, P>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
                                                 local % it.a.n_dblocks, local / it.a.n_dblocks);
   }
 }
@@ -461,34 +565,29 @@ __global__ __launch_bounds__(256) void ring_update_kernel(const TIN* __restrict_
   ring[(int64_t)c * R + (seen + t) % R] = v;
 }
 
-template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC>
+template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
 hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit32, size_t lds,
                       hipStream_t s) {
+  // the LDS limit was raised when the plan was created (dedisp_prepare), so
+  // a launch makes no attribute call and is safe inside stream capture
   const unsigned grid = (unsigned)a.n_dblocks * (unsigned)a.n_ttiles;
-  auto kern = dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC>;
-  // raise the kernel's LDS limit once, on its first (normally eager) launch,
-  // so that no attribute call happens while a stream is being captured
-  static int lds_set = 0;
-  if (lds > 64 * 1024 && lds_set < (int)lds) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    lds_set = 160 * 1024;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, s, a, relb, fit32);
+  hipLaunchKernelGGL((dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC, P>), dim3(grid), dim3(64 * NW), lds, s,
+                     a, relb, fit32);
   return hipGetLastError();
 }
 
 // Compiled tilings: (waves per workgroup, DMs per wave, float4 groups per
-// lane, channels per LDS stage).
-#define MBTP_TILINGS(X) X(4, 4, 2, 4) X(8, 4, 2, 8) X(8, 4, 1, 4) X(4, 8, 1, 4) X(8, 4, 2, 4) X(8, 8, 1, 4)
+// lane, channels per LDS stage, P: bit 0 rolling accumulation, bit 1 double-
+// buffered LDS stages).
+#define MBTP_TILINGS(X) X(8, 4, 2, 4, 2) X(16, 2, 2, 4, 2) X(8, 2, 2, 4, 2) X(16, 2, 2, 2, 2) \
+  X(8, 4, 2, 8, 0) X(8, 4, 2, 2, 2) X(8, 4, 2, 4, 3) X(16, 2, 2, 4, 3)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,
                         const float* fit32, size_t lds, hipStream_t s) {
-#define MBTP_TILE(NW_, G_, Q_, BC_) \
-  if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_) \
-    return launch_one<TIN, CLEAN, RING, NW_, G_, Q_, BC_>(a, relb, fit32, lds, s);
+#define MBTP_TILE(NW_, G_, Q_, BC_, P_) \
+  if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_ && t.P == P_) \
+    return launch_one<TIN, CLEAN, RING, NW_, G_, Q_, BC_, P_>(a, relb, fit32, lds, s);
   MBTP_TILINGS(MBTP_TILE)
 #undef MBTP_TILE
   return hipErrorInvalidValue;
@@ -496,7 +595,7 @@ hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* rel
 
 }  // namespace
 
-#define MBTP_LIST(NW_, G_, Q_, BC_) {NW_, G_, Q_, BC_},
+#define MBTP_LIST(NW_, G_, Q_, BC_, P_) {NW_, G_, Q_, BC_, P_},
 static const Tiling kTilings[] = {MBTP_TILINGS(MBTP_LIST)};
 #undef MBTP_LIST
 
@@ -552,41 +651,56 @@ hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, 
 }
 
 namespace {
-template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC>
-hipError_t launch_batch_one(BatchArgs& b, size_t lds, hipStream_t s) {
-  auto kern = dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC>;
-  hipError_t e;
-  // attribute and occupancy queries once per instantiation and LDS size (on
-  // the first, normally eager, launch), none while a stream is captured
-  static int lds_set = 0;
-  static size_t occ_lds = 0;
-  static int occ = 0, cus = 0;
-  if (lds > 64 * 1024 && lds_set == 0) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    lds_set = 1;
-  }
-  if (occ_lds != lds || cus == 0) {
-    int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern),
-                                                          64 * NW, lds)) != hipSuccess) return e;
-    occ_lds = lds;
-  }
-  const int per_cu = occ < 1 ? 1 : occ;
-  const int grid = b.total < cus * per_cu ? b.total : cus * per_cu;
+template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC, int P>
+hipError_t launch_batch_one(BatchArgs& b, size_t lds, int grid_cap, hipStream_t s) {
+  const int grid = b.total < grid_cap ? b.total : grid_cap;
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, b.counter);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, s, b);
+  hipLaunchKernelGGL((dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC, P>), dim3(grid), dim3(64 * NW), lds, s, b);
   return hipGetLastError();
 }
 
+// Raises the LDS limit of every kernel variant of one (storage type, tiling)
+// and returns the persistent kernel's resident workgroups per CU at `lds`
+// bytes, without and with cleaning.
+template <typename TIN, int NW, int G, int Q, int BC, int P>
+hipError_t prepare_one(size_t lds, int occ[2]) {
+  const void* ks[6] = {
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, false, NW, G, Q, BC, P>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, true, NW, G, Q, BC, P>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, false, NW, G, Q, BC, P>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, true, NW, G, Q, BC, P>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, false, NW, G, Q, BC, P>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, true, NW, G, Q, BC, P>)};
+  hipError_t e;
+  for (const void* k : ks) {
+    // dynamic + static LDS of a workgroup must fit the CU's 160 KiB
+    hipFuncAttributes fa;
+    if ((e = hipFuncGetAttributes(&fa, k)) != hipSuccess) return e;
+    const int dyn_max = 160 * 1024 - (int)fa.sharedSizeBytes;
+    if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_max)) != hipSuccess)
+      return e;
+  }
+  for (int c = 0; c < 2; ++c)
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[c], ks[4 + c], 64 * NW, lds)) != hipSuccess)
+      return e;
+  return hipSuccess;
+}
+
+template <typename TIN>
+hipError_t prepare_tiled(const Tiling& t, size_t lds, int occ[2]) {
+#define MBTP_TILE(NW_, G_, Q_, BC_, P_) \
+  if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_ && t.P == P_) \
+    return prepare_one<TIN, NW_, G_, Q_, BC_, P_>(lds, occ);
+  MBTP_TILINGS(MBTP_TILE)
+#undef MBTP_TILE
+  return hipErrorInvalidValue;
+}
+
 template <typename TIN, bool CLEAN>
-hipError_t launch_batch_tiled(const Tiling& t, BatchArgs& b, size_t lds, hipStream_t s) {
-#define MBTP_TILE(NW_, G_, Q_, BC_) \
-  if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_) \
-    return launch_batch_one<TIN, CLEAN, NW_, G_, Q_, BC_>(b, lds, s);
+hipError_t launch_batch_tiled(const Tiling& t, BatchArgs& b, size_t lds, int grid_cap, hipStream_t s) {
+#define MBTP_TILE(NW_, G_, Q_, BC_, P_) \
+  if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_ && t.P == P_) \
+    return launch_batch_one<TIN, CLEAN, NW_, G_, Q_, BC_, P_>(b, lds, grid_cap, s);
   MBTP_TILINGS(MBTP_TILE)
 #undef MBTP_TILE
   return hipErrorInvalidValue;
@@ -594,11 +708,19 @@ hipError_t launch_batch_tiled(const Tiling& t, BatchArgs& b, size_t lds, hipStre
 }  // namespace
 
 hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds,
-                               hipStream_t s) {
+                               int grid_cap, hipStream_t s) {
   switch (dtype) {
-    case 0: return clean ? launch_batch_tiled<uint8_t, true>(t, b, lds, s) : launch_batch_tiled<uint8_t, false>(t, b, lds, s);
-    case 1: return clean ? launch_batch_tiled<__half, true>(t, b, lds, s) : launch_batch_tiled<__half, false>(t, b, lds, s);
-    default: return clean ? launch_batch_tiled<float, true>(t, b, lds, s) : launch_batch_tiled<float, false>(t, b, lds, s);
+    case 0: return clean ? launch_batch_tiled<uint8_t, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<uint8_t, false>(t, b, lds, grid_cap, s);
+    case 1: return clean ? launch_batch_tiled<__half, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<__half, false>(t, b, lds, grid_cap, s);
+    default: return clean ? launch_batch_tiled<float, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<float, false>(t, b, lds, grid_cap, s);
+  }
+}
+
+hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]) {
+  switch (dtype) {
+    case 0: return prepare_tiled<uint8_t>(t, lds, occ);
+    case 1: return prepare_tiled<__half>(t, lds, occ);
+    default: return prepare_tiled<float>(t, lds, occ);
   }
 }
 

@@ -144,6 +144,7 @@ static_assert(sizeof(BatchArgs) <= 4096, "batch arguments exceed the kernel argu
 struct Tiling {
   int NW, G, Q, BC;   // waves per workgroup, DMs per wave, float4 groups per lane,
                       // channels per LDS stage
+  int P;              // bit 0: rolling accumulation loop; bit 1: two LDS stages
   int BD() const { return NW * G; }
   int BT() const { return 256 * Q; }
   int threads() const { return 64 * NW; }
@@ -165,9 +166,14 @@ hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, cons
                          hipStream_t s);
 
 // One persistent launch over the tiles of all items (same dtype, cleaning
-// and tiling); lds = the largest item's LDS.
+// and tiling); lds = the largest item's LDS; at most grid_cap workgroups.
 hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds,
-                               hipStream_t s);
+                               int grid_cap, hipStream_t s);
+
+// At plan creation: raises the LDS limit of every dedispersion kernel of the
+// storage type and tiling, and returns the persistent kernel's resident
+// workgroups per CU at `lds` bytes (occ[0] without, occ[1] with cleaning).
+hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]);
 
 // Writes the chunk's last min(L, R) cleaned samples into the ring at the
 // positions given by the beam's device-side sample count, then advances it.

@@ -89,11 +89,14 @@ struct mb_plan {
   std::vector<int32_t> h_delays;
   int32_t* d_delays = nullptr;
   int32_t* d_relb = nullptr;
-  Tiling tiling{4, 4, 2, 4};
+  Tiling tiling{4, 4, 2, 4, 0};
+  int tile_index = 1;          // 1-based index in the compiled list
   int rs = 0;
   size_t lds = 0;
   int n_dblocks = 0;
   int relb_ld = 0;
+  int cus = 0;                 // compute units of the plan's device
+  int batch_occ[2] = {1, 1};   // persistent workgroups per CU (no cleaning, cleaning)
 };
 
 struct mb_beam {
@@ -120,7 +123,7 @@ int32_t span_max(const mb_plan& p, int BD) {
   return m;
 }
 
-constexpr size_t kMaxLds = 160 * 1024;   // gfx950 LDS per workgroup
+constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, less the persistent kernel's static LDS
 
 // LDS copy length: the largest window start (span + 3, rounded down to 4)
 // plus the tile, plus the quad read after the last one.
@@ -128,15 +131,27 @@ void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
   const int sp = span_max(p, t.BD());
   rs = (t.BT() + sp + 7 + 3) & ~3;
   // four shifted copies per channel, then the block's [BC][BD] offsets
-  lds = (size_t)t.BC * 4 * rs * sizeof(float) + (size_t)t.BC * t.BD() * sizeof(int32_t);
+  lds = ((size_t)t.BC * 4 * rs * sizeof(float) + (size_t)t.BC * t.BD() * sizeof(int32_t)) *
+        ((t.P & 2) ? 2 : 1);   // P bit 1: two stages (double buffer)
 }
 
 // A tiling fits when its LDS fits and each lane's prefetch registers cover
 // its share of a channel block.
+// Staging registers: with NW >= BC, WPR waves split a row of rs/4 quads into
+// ranges of qw quads (one quad of overlap) and each lane holds KM of them;
+// with NW < BC a wave stages BC/NW whole rows.  Same rule as the kernel.
 bool tiling_fits(const Tiling& t, int rs, size_t lds) {
-  const int rows_per_wave = t.NW >= t.BC ? 1 : t.BC / t.NW;
-  const int quads_per_lane = ((rs / 4) + 63) / 64;
-  return lds <= kMaxLds && rows_per_wave * quads_per_lane <= kStageQuads;
+  const int rs4 = rs / 4;
+  if (lds > kMaxLds || rs4 > 64 * kStageQuads) return false;
+  if (t.NW >= t.BC) {
+    const int wpr = t.NW / t.BC;
+    const int qwmax = (64 * kStageQuads - 1 + wpr - 1) / wpr + 1;
+    const int km = (qwmax + 63) / 64;
+    const int qw = wpr > 1 ? (rs4 - 1 + wpr - 1) / wpr + 1 : rs4;
+    return qw <= 64 * km;
+  }
+  const int rows_per_wave = t.BC / t.NW;
+  return rows_per_wave * ((rs4 + 63) / 64) <= kStageQuads;
 }
 
 mb_status choose_tiling(mb_plan& p) {
@@ -159,6 +174,7 @@ mb_status choose_tiling(mb_plan& p) {
     if (pick < 0) return fail(MB_EINVAL, "the DM step is too coarse for the compiled tilings (LDS)");
   }
   p.tiling = tiling_at(pick);
+  p.tile_index = pick + 1;
   tiling_geometry(p, p.tiling, p.rs, p.lds);
   p.n_dblocks = (p.desc.ndms + p.tiling.BD() - 1) / p.tiling.BD();
   return MB_OK;
@@ -254,7 +270,9 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
     delete p;
     return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", tb + rb);
   }
-  e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
+  e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e == hipSuccess) e = dedisp_prepare(d.in_dtype, p->tiling, p->lds, p->batch_occ);
+  if (e == hipSuccess) e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->relb_ld, p->d_relb, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
@@ -283,7 +301,15 @@ mb_status dedisp_plan_info(const mb_plan* plan, mb_plan_info* info) {
   info->dm_block = plan->tiling.BD();
   info->time_tile = plan->tiling.BT();
   info->chan_block = plan->tiling.BC;
+  info->tile_index = plan->tile_index;
+  info->waves = plan->tiling.NW;
   info->lds_bytes = (int64_t)plan->lds;
+  return ok();
+}
+
+mb_status dedisp_tilings(int32_t* count) {
+  if (!count) return fail(MB_EINVAL, "count is NULL");
+  *count = n_tilings();
   return ok();
 }
 
@@ -562,7 +588,8 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
     if (it.plan->desc.in_dtype != p0->desc.in_dtype)
       return fail(MB_EINVAL, "item %d: all items of a batch share the storage type", i);
     const Tiling& t = it.plan->tiling;
-    if (t.NW != p0->tiling.NW || t.G != p0->tiling.G || t.Q != p0->tiling.Q || t.BC != p0->tiling.BC)
+    if (t.NW != p0->tiling.NW || t.G != p0->tiling.G || t.Q != p0->tiling.Q || t.BC != p0->tiling.BC ||
+        t.P != p0->tiling.P)
       return fail(MB_EINVAL, "item %d: all plans of a batch must use the same tiling (tile_hint)", i);
     if ((it.d_rfi_state != nullptr) != clean0)
       return fail(MB_EINVAL, "item %d: either every item or none has an RFI state", i);
@@ -585,6 +612,7 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
     b.counter = reinterpret_cast<int*>(static_cast<char*>(d_work) + 256 * (size_t)l);
     size_t lds = 0;
     int32_t total = 0;
+    int grid_cap = 1 << 30;
     for (int32_t k = l * kMaxBatch; k < nitems && k < (l + 1) * kMaxBatch; ++k) {
       const Prepared& q = P[order[k]];
       if (q.nout <= 0) continue;
@@ -595,9 +623,12 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
       bi.tile0 = total;
       total += q.a.n_dblocks * q.a.n_ttiles;
       if (q.plan->lds > lds) lds = q.plan->lds;
+      const int occ = q.plan->batch_occ[clean0 ? 1 : 0];
+      const int cap = q.plan->cus * (occ < 1 ? 1 : occ);
+      if (cap < grid_cap) grid_cap = cap;
     }
     b.total = total;
-    if (total > 0) HIP_TRY(launch_dedisp_batch(p0->desc.in_dtype, clean0, p0->tiling, b, lds, s));
+    if (total > 0) HIP_TRY(launch_dedisp_batch(p0->desc.in_dtype, clean0, p0->tiling, b, lds, grid_cap, s));
   }
   for (int32_t i = 0; i < nitems; ++i) {
     mb_status st = finish_item(P[i], s);
