@@ -85,17 +85,26 @@ def traffic_summary(fetch_csv: str, write_csv: str) -> None:
 
     f = per_kernel(fetch_csv, "FETCH_SIZE")
     w = per_kernel(write_csv, "WRITE_SIZE")
-    f_scale = CALIB_BYTES / float(np.mean(f["copy"]))
-    w_scale = CALIB_BYTES / float(np.mean(w["copy"]))
+    # the calibration copy is the largest copy dispatch of the run (the
+    # plan's small table upload is another)
+    f_scale = CALIB_BYTES / float(np.max(f["copy"]))
+    w_scale = CALIB_BYTES / float(np.max(w["copy"]))
     fetch = float(np.mean(f["dedisp"])) * f_scale
     write = float(np.mean(w["dedisp"])) * w_scale
     path = os.path.join(ROOT, "profiles", "dedisp_traffic.txt")
     with open(path, "w") as fh:
         fh.write("# HBM traffic of one dedisp_kernel launch, bench workload "
                  "(1024 ch x 65536 samples x 640 DMs, f32, RFI on)\n")
-        fh.write("# from: rocprofv3 --pmc FETCH_SIZE ... and --pmc WRITE_SIZE ... -- python3 bench.py "
-                 "--steps 3 --warmup 1 --no-cpu-baseline --calib-copy\n")
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            fh.write(f"# command: cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {ctr} --output-format csv "
+                     f"-d OUT -o bench -- python3 REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline "
+                     f"--calib-copy\n")
+        fh.write("# then: python bench.py --traffic-from OUT_FETCH/bench_counter_collection.csv "
+                 "OUT_WRITE/bench_counter_collection.csv\n")
         fh.write(f"kernel_source_hash={_kernel_hash()}\n")
+        fh.write(f"# counter reading of the {CALIB_BYTES >> 20} MiB calibration copy, KiB: fetch "
+                 f"{np.max(f['copy']) / 1024:.0f}, write {np.max(w['copy']) / 1024:.0f}\n")
+        fh.write(f"# dedisp_kernel dispatches: {len(f['dedisp'])} (fetch), {len(w['dedisp'])} (write)\n")
         fh.write(f"fetch_scale={f_scale:.4f}\nwrite_scale={w_scale:.4f}\n")
         fh.write(f"fetch_bytes={fetch:.0f}\nwrite_bytes={write:.0f}\n")
         fh.write(f"bytes_per_launch={fetch + write:.0f}\n")

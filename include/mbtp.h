@@ -21,7 +21,10 @@
  *    by one stream at a time.
  *  - Filterbanks are x[c][t]: channel c's samples are contiguous in time,
  *    row c starts at element c*ld.  The device pointer must be 16-byte
- *    aligned and ld a multiple of 4 elements.
+ *    aligned and ld a multiple of 4 elements, and the buffer must hold
+ *    nchans*ld elements: kernels read whole aligned groups of 4 samples, so
+ *    when nsamps is not a multiple of 4 the last group of a row reaches into
+ *    the row's padding (those values are never used).
  *  - Every call validates its arguments before enqueuing anything; on an
  *    error nothing is enqueued, the call returns a non-zero mb_status and
  *    mb_last_error() (per thread) describes it.  No C++ exception crosses
@@ -182,7 +185,9 @@ mb_status dedisp_tilings(int32_t* count);
 void mb_rfi_defaults(mb_rfi_params* p);
 
 /* Size and layout of the caller-owned device buffer that holds one RFI
- * pass's statistics, fitted bandpass and flags for nsamps samples. */
+ * pass's statistics, fitted bandpass and flags for nsamps samples.  The
+ * size never decreases with nsamps, so a buffer sized for the longest chunk
+ * serves every shorter chunk of the same plan. */
 mb_status rfi_state_layout(const mb_plan* plan, int64_t nsamps, mb_rfi_layout* layout);
 
 /* Runs the three stages of Sec. 2.2.1, with the plan's RFI factors, on d_in

@@ -72,6 +72,7 @@ template <> struct Quad<uint8_t> {
 template <typename TIN, bool RING> struct Staged {
   typename Quad<TIN>::Raw raw;       // chunk values (f32: chunk or ring values)
   float4 rv;                         // ring values (u8 / f16 with a ring only)
+  uint32_t g;                        // spectrum flags of the 4 samples (cleaning)
   int32_t t;                         // chunk index of the first sample: < 0 ring,
                                      // >= L (or kNoQuad) nothing to stage
 };
@@ -83,67 +84,71 @@ __device__ inline uint32_t chunk_of(const CleanView& cv, int64_t t) {
 }
 
 // Row of one staged channel: where its window starts and, for cleaning, the
-// 64 chunk flags around the window and whether any spectrum in it is flagged.
+// 64 chunk flags around the window.
 struct RowMeta {
   int64_t a;        // virtual index of the window's first sample (aligned)
   uint32_t m_lo, m_hi;  // chunk flags j0..j0+63 (bit per chunk)
   int32_t j0;
-  int32_t g_lo, g_hi;   // prefix counts of flagged spectra bracketing the window
 };
 
-// Issues the load of the quad at virtual index tau (a multiple of 4); `live`
-// is false for lanes past the end of their range.  Rows are ld >= L apart
-// with ld a multiple of 4, so the aligned quad holding any chunk sample lies
-// inside its row.
-template <typename TIN, bool RING>
+// Issues the load of the quad whose first sample has chunk index t (a
+// multiple of 4; t < 0: the quad lies in the ring, which precedes the chunk
+// in virtual time); `live` is false for lanes past the end of their range.
+// Rows are ld >= L apart with ld a multiple of 4, so the aligned quad
+// holding any chunk sample lies inside its row.  Indices are 32-bit and
+// relative to the row bases, which are uniform.  pv = ring position of
+// chunk sample 0.
+template <typename TIN, bool CLEAN, bool RING>
 __device__ inline void issue(Staged<TIN, RING>& s, const DedispArgs& A, const TIN* xrow,
-                             const float* ringrow, int64_t tau, bool live, int64_t p0) {
-  const int64_t v = RING ? A.ring_valid : 0;
-  const int64_t t = tau - v;
-  const bool in_chunk = live && t >= 0 && t < A.L;
-  const TIN* px = xrow + (in_chunk ? t : 0);
+                             const float* ringrow, int32_t t, bool live, int32_t pv) {
+  const int32_t L = (int32_t)A.L;
+  const bool in_chunk = live && (uint32_t)t < (uint32_t)L;
+  const uint32_t off = in_chunk ? (uint32_t)t : 0u;
+  // the 4 spectrum flags of the quad (the flag array is padded to 256 bytes)
+  if (CLEAN) s.g = *reinterpret_cast<const uint32_t*>(A.clean.gflags + off);
   if constexpr (RING) {
-    const bool in_ring = live && tau < v;
-    int64_t p = p0 + tau;
-    if (p >= A.R) p -= A.R;
+    const bool in_ring = live && t < 0;
+    int32_t p = pv + t;
+    if (p < 0) p += (int32_t)A.R;
+    const uint32_t poff = in_ring ? (uint32_t)p : 0u;
     if constexpr (std::is_same<TIN, float>::value) {
-      const float* pr = in_ring ? ringrow + p : px;
+      const float* pr = in_ring ? ringrow + poff : xrow + off;
       s.raw = *reinterpret_cast<const float4*>(pr);
     } else {
-      s.raw = Quad<TIN>::load(px);
+      s.raw = Quad<TIN>::load(xrow + off);
       if (A.ring_valid > 0)        // uniform: the ring exists
-        s.rv = *reinterpret_cast<const float4*>(ringrow + (in_ring ? p : 0));
+        s.rv = *reinterpret_cast<const float4*>(ringrow + poff);
       else
         s.rv = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    s.t = !live ? kNoQuad : (in_ring ? -1 : (int32_t)min(t, (int64_t)kNoQuad));
+    s.t = !live ? kNoQuad : (in_ring ? -1 : min(t, kNoQuad));
   } else {
-    s.raw = Quad<TIN>::load(px);
-    s.t = (live && t < A.L) ? (int32_t)t : kNoQuad;
+    s.raw = Quad<TIN>::load(xrow + off);
+    s.t = (live && t < L) ? t : kNoQuad;
   }
 }
 
 // Widens and cleans a landed quad: samples past the chunk end are 0; ring
 // samples were cleaned when they entered the ring.  Chunk flags come from
-// the row's 64-bit mask; spectrum flags are read per quad only when the
-// window holds any.
+// the row's 64-bit mask, spectrum flags from the word loaded with the quad.
 template <typename TIN, bool CLEAN, bool RING>
 __device__ inline float4 finish(const Staged<TIN, RING>& s, const DedispArgs& A, const RowMeta& rm,
-                                bool any_g, float fit) {
+                                float fit) {
   float4 f;
   if constexpr (std::is_same<TIN, float>::value) f = s.raw;
   else f = Quad<TIN>::widen(s.raw);
   const int32_t t = s.t;
+  const int32_t L = (int32_t)A.L;                            // <= 2^30: 32-bit compares
   const bool ring = RING && t < 0;
-  const int32_t tc = (t < 0 || t >= A.L) ? 0 : t;           // in-range stand-in for addressing
-  bool z0 = t + 0 >= A.L, z1 = t + 1 >= A.L, z2 = t + 2 >= A.L, z3 = t + 3 >= A.L;
+  const int32_t tc = (uint32_t)t < (uint32_t)L ? t : 0;      // in-range stand-in for the chunk index
+  const int32_t left = L - t;                                // valid samples from t on
+  bool z0 = left <= 0, z1 = left <= 1, z2 = left <= 2, z3 = left <= 3;
   float sub = 0.0f;
   if (CLEAN) {
     const int jr = (int)chunk_of(A.clean, tc) - rm.j0;       // 0..63 inside the window
     const uint32_t word = jr < 32 ? rm.m_lo : rm.m_hi;
     const bool cf = ((word >> (jr & 31)) & 1u) != 0;
-    uint32_t g = 0;
-    if (any_g) g = *reinterpret_cast<const uint32_t*>(A.clean.gflags + tc);
+    const uint32_t g = s.g;
     z0 = z0 || cf || (g & 0xffu); z1 = z1 || cf || (g & 0xff00u);
     z2 = z2 || cf || (g & 0xff0000u); z3 = z3 || cf || (g & 0xff000000u);
     sub = fit;
@@ -215,6 +220,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     const int64_t sn = *A.seen_dev;
     p0 = (sn - vring) % A.R;
   }
+  // ring position of chunk sample 0
+  const int32_t pv = (RING && A.R > 0) ? (int32_t)((p0 + vring) % A.R) : 0;
   const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;   // DM d0's delays
   // LDS: one stage (or two, double-buffered) of BC rows x 4 copies x RS
   // samples followed by the stage's [BC][BD] window offsets
@@ -246,7 +253,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       int64_t tlo = a - vring, thi = a - vring + RS + 4;
       tlo = tlo < 0 ? 0 : (tlo > A.L ? A.L : tlo);
       thi = thi < 0 ? 0 : (thi > A.L ? A.L : thi);
-      if (thi <= tlo) { m.j0 = 0; m.m_lo = m.m_hi = 0; m.g_lo = m.g_hi = 0; return; }
+      if (thi <= tlo) { m.j0 = 0; m.m_lo = m.m_hi = 0; return; }
       const int jlo = (int)chunk_of(A.clean, tlo);
       const int w0 = jlo >> 5;
       m.j0 = w0 * 32;
@@ -254,8 +261,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       const uint32_t* cb = A.clean.cbits + (int64_t)c * A.clean.JW + vz;
       m.m_lo = cb[w0];
       m.m_hi = (w0 + 1 < A.clean.JW) ? cb[w0 + 1] : 0u;
-      m.g_lo = A.clean.gspan[(tlo >> 8) + vz];
-      m.g_hi = A.clean.gspan[((thi - 1) >> 8) + 1 + vz];
     }
   };
 
@@ -266,6 +271,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       if (c < C) {
         const int base = __builtin_amdgcn_readfirstlane(basen[rr]);
         const int64_t a = t0 + (base & ~3);
+        const int32_t aw = (int32_t)(a - vring);     // chunk index of the window start
         const TIN* xrow = static_cast<const TIN*>(A.x) + (int64_t)c * A.ld;
         const float* ringrow = RING ? A.ring + (int64_t)c * A.R : nullptr;
         load_meta(rm[rr], c, a);
@@ -273,7 +279,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           const int m = m0 + lane + 64 * k;
-          issue<TIN, RING>(st[rr][k], A, xrow, ringrow, a + 4 * m, m < mend, p0);
+          issue<TIN, CLEAN, RING>(st[rr][k], A, xrow, ringrow, aw + 4 * m, m < mend, pv);
         }
       }
       const int cn = cb0 + BC + row_of(rr);
@@ -308,10 +314,9 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           *reinterpret_cast<float4*>(row + 4 * m) = make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
         const float fit = CLEAN ? fitn[rr] : 0.0f;
-        const bool any_g = CLEAN && (__builtin_amdgcn_readfirstlane(rm[rr].g_hi - rm[rr].g_lo) != 0);
         float4 lo[KM];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], any_g, fit);
+        for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], fit);
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           float4 hi;
@@ -579,8 +584,8 @@ hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit
 // Compiled tilings: (waves per workgroup, DMs per wave, float4 groups per
 // lane, channels per LDS stage, P: bit 0 rolling accumulation, bit 1 double-
 // buffered LDS stages).
-#define MBTP_TILINGS(X) X(8, 4, 2, 4, 2) X(16, 2, 2, 4, 2) X(8, 2, 2, 4, 2) X(16, 2, 2, 2, 2) \
-  X(8, 4, 2, 8, 0) X(8, 4, 2, 2, 2) X(8, 4, 2, 4, 3) X(16, 2, 2, 4, 3)
+#define MBTP_TILINGS(X) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(16, 2, 2, 4, 2) X(8, 4, 2, 4, 2) \
+  X(8, 2, 2, 4, 2) X(16, 2, 2, 2, 2) X(8, 4, 2, 2, 2) X(8, 4, 2, 4, 3)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,

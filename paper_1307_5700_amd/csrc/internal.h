@@ -47,10 +47,11 @@ inline RfiGeom rfi_geometry(int64_t C, int64_t T, int64_t W) {
   g.C = C; g.T = T; g.W = W;
   g.J = (T + W - 1) / W;
   g.nspans = (T + kSpan - 1) / kSpan;
-  // channels per statistics workgroup: enough workgroups to fill the chip,
-  // few enough partial spectrum sums to keep the second pass cheap
+  // channels per statistics workgroup: at most 8 groups of partial spectrum
+  // sums, chosen from C alone, so the state size never decreases with T (a
+  // buffer sized for the longest chunk holds any shorter one)
   int64_t cg = 64;
-  while (cg < 512 && (C + cg - 1) / cg > 8 && g.nspans * ((C + 2 * cg - 1) / (2 * cg)) >= 2048) cg *= 2;
+  while (cg < 512 && (C + cg - 1) / cg > 8) cg *= 2;
   g.CG = cg;
   g.ngroups = (C + cg - 1) / cg;
   size_t o = 0;

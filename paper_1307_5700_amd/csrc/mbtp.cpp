@@ -123,6 +123,9 @@ int32_t span_max(const mb_plan& p, int BD) {
   return m;
 }
 
+// chunk lengths up to 2^30 keep every window-relative sample index of the
+// kernels (chunk, ring and staging margin) inside 32 bits
+constexpr int64_t kMaxSamps = int64_t(1) << 30;
 constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, less the persistent kernel's static LDS
 
 // LDS copy length: the largest window start (span + 3, rounded down to 4)
@@ -197,7 +200,7 @@ mb_status validate_input(const mb_plan* plan, const void* d_in, int64_t nsamps, 
   if (!d_in) return fail(MB_EINVAL, "input pointer is NULL");
   if (!check_aligned(d_in, 16)) return fail(MB_EINVAL, "input pointer must be 16-byte aligned");
   if (nsamps < 1) return fail(MB_EINVAL, "nsamps must be >= 1");
-  if (nsamps > INT32_MAX) return fail(MB_EINVAL, "nsamps must be < 2^31");
+  if (nsamps > kMaxSamps) return fail(MB_EINVAL, "nsamps must be <= 2^30");
   if (ld < nsamps || ld % 4 != 0) return fail(MB_EINVAL, "ld (%lld) must be >= nsamps and a multiple of 4", (long long)ld);
   return MB_OK;
 }
@@ -321,7 +324,7 @@ mb_status dedisp_plan_delays(const mb_plan* plan, int32_t* h_delays) {
 
 mb_status rfi_state_layout(const mb_plan* plan, int64_t nsamps, mb_rfi_layout* layout) {
   if (!plan || !layout) return fail(MB_EINVAL, "plan and layout must not be NULL");
-  if (nsamps < 1 || nsamps > INT32_MAX) return fail(MB_EINVAL, "nsamps must be in 1..2^31-1");
+  if (nsamps < 1 || nsamps > kMaxSamps) return fail(MB_EINVAL, "nsamps must be in 1..2^30");
   const RfiGeom g = rfi_geometry(plan->desc.nchans, nsamps, plan->desc.rfi.window);
   layout->total_bytes = g.total;
   layout->fit_f64 = g.off_fit;

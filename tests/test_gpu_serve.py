@@ -90,6 +90,14 @@ def test_admission_waits_for_budget():
     assert srv.used_bytes() <= budget
 
 
+def test_rfi_state_size_never_decreases_with_chunk_length():
+    """A slot sized for the longest chunk must hold any shorter chunk."""
+    A = api()
+    plan = A.Plan.from_beam(synth.served_beams(1)[0])
+    sizes = [plan.rfi_layout(n).total_bytes for n in range(4096, 65536 + 1, 1024)]
+    assert all(b >= a for a, b in zip(sizes, sizes[1:]))
+
+
 def test_budget_formula():
     from paper_1307_5700_amd import serve
     A = api()
