@@ -320,8 +320,10 @@ def bench_serve(args):
     beams = synth.served_beams(32)
     plan = A.Plan.from_beam(beams[0])
     rng = np.random.default_rng(7)
-    # a pool of distinct uint8 noise blocks; each request takes a slice
-    pool = [synth.quantise(synth.noise((plan.nchans, 65536), seed=900 + k), "u8") for k in range(4)]
+    # a pool of distinct uint8 noise blocks in pinned host memory (where a
+    # receiver would have written them); each request is a view of one
+    pool = [torch.from_numpy(synth.quantise(synth.noise((plan.nchans, 65536), seed=900 + k), "u8")).pin_memory()
+            for k in range(4)]
     lengths = np.arange(8192, 65536 + 1, 1024)
 
     def chunks(n_per_beam):
@@ -331,8 +333,8 @@ def bench_serve(args):
             for _ in range(n_per_beam):
                 L = int(rng.choice(lengths))
                 blk = pool[int(rng.integers(0, len(pool)))]
-                a = int(rng.integers(0, 65536 - L + 1)) // 4 * 4
-                lst.append(blk[:, a:a + L])          # a view: no host copy
+                # a contiguous [C][L] view of a pinned block: no host copy
+                lst.append(blk.view(-1)[:plan.nchans * L].view(plan.nchans, L))
             out[i] = lst
         return out
 
@@ -345,7 +347,7 @@ def bench_serve(args):
             srv.add_beam(i)
         # warm-up: one short chunk per beam fills the rings
         for i in range(len(beams)):
-            srv.submit(serve.Request(beam_id=i, data=pool[0][:, :8192],
+            srv.submit(serve.Request(beam_id=i, data=pool[0].view(-1)[:plan.nchans * 8192].view(plan.nchans, 8192),
                                      t_arrival=time.perf_counter()))
         srv.drain()
         srv.done.clear()

@@ -243,6 +243,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   RowMeta rm[RPW];
   int basen[RPW];        // s[d0][c] of the row in the block after next (vector load, lands early)
   float fitn[RPW];       // bandpass value of the row being staged (loaded with its quads)
+  int32_t rowt[RPW];     // chunk index of the staged row's window start (uniform)
   int offreg = 0;
 
   // Cleaning metadata of row c (vector loads: they count on vmcnt only, so
@@ -272,6 +273,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         const int base = __builtin_amdgcn_readfirstlane(basen[rr]);
         const int64_t a = t0 + (base & ~3);
         const int32_t aw = (int32_t)(a - vring);     // chunk index of the window start
+        rowt[rr] = aw;
         const TIN* xrow = static_cast<const TIN*>(A.x) + (int64_t)c * A.ld;
         const float* ringrow = RING ? A.ring + (int64_t)c * A.R : nullptr;
         load_meta(rm[rr], c, a);
@@ -315,8 +317,31 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       } else {
         const float fit = CLEAN ? fitn[rr] : 0.0f;
         float4 lo[KM];
+        // Fast path (uniform per row): the wave's quads all lie inside the
+        // chunk and none of their chunks or spectra is flagged, so a quad
+        // needs only widening and the bandpass subtraction.
+        const int32_t t_lo = rowt[rr] + 4 * m0, t_hi = rowt[rr] + 4 * mend;
+        bool fast = t_lo >= 0 && t_hi <= (int32_t)A.L;
+        if (CLEAN) {
+          uint32_t gor = 0;
 #pragma unroll
-        for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], fit);
+          for (int k = 0; k < KM; ++k) gor |= st[rr][k].g;
+          const uint32_t mbits = __builtin_amdgcn_readfirstlane(rm[rr].m_lo | rm[rr].m_hi);
+          fast = fast && mbits == 0 && __builtin_amdgcn_ballot_w64(gor != 0) == 0;
+        }
+        if (fast) {
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            float4 f;
+            if constexpr (std::is_same<TIN, float>::value) f = st[rr][k].raw;
+            else f = Quad<TIN>::widen(st[rr][k].raw);
+            if (CLEAN) { f.x -= fit; f.y -= fit; f.z -= fit; f.w -= fit; }
+            lo[k] = f;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], fit);
+        }
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           float4 hi;
@@ -584,8 +609,11 @@ hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit
 // Compiled tilings: (waves per workgroup, DMs per wave, float4 groups per
 // lane, channels per LDS stage, P: bit 0 rolling accumulation, bit 1 double-
 // buffered LDS stages).
-#define MBTP_TILINGS(X) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(16, 2, 2, 4, 2) X(8, 4, 2, 4, 2) \
-  X(8, 2, 2, 4, 2) X(16, 2, 2, 2, 2) X(8, 4, 2, 2, 2) X(8, 4, 2, 4, 3)
+// The plan takes the first that fits its LDS and staging limits: the last
+// three, with 16 and 8 DMs per block, serve DM grids whose delay spread per
+// DM step is large (coarse steps, slow sampling).
+#define MBTP_TILINGS(X) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(16, 2, 2, 4, 2) X(8, 4, 2, 8, 1) \
+  X(8, 4, 2, 4, 2) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,

@@ -145,7 +145,7 @@ void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
 // with NW < BC a wave stages BC/NW whole rows.  Same rule as the kernel.
 bool tiling_fits(const Tiling& t, int rs, size_t lds) {
   const int rs4 = rs / 4;
-  if (lds > kMaxLds || rs4 > 64 * kStageQuads) return false;
+  if (lds > kMaxLds) return false;
   if (t.NW >= t.BC) {
     const int wpr = t.NW / t.BC;
     const int qwmax = (64 * kStageQuads - 1 + wpr - 1) / wpr + 1;

@@ -63,7 +63,8 @@ def max_chunk_for_budget(plan: A.Plan, budget_bytes: int) -> int:
 @dataclass
 class Request:
     beam_id: int
-    data: np.ndarray                  # host chunk [C][L]
+    data: "np.ndarray | torch.Tensor"  # host chunk [C][L]: numpy, or a pinned CPU tensor
+                                       # (copied to the device directly, no staging copy)
     t_arrival: float
     seq: int = 0
     t_done: float = 0.0
@@ -79,8 +80,10 @@ class _Slot:
     def __init__(self, plan: A.Plan, max_chunk: int, capacity: int):
         self.plan = plan
         tdt = A.TORCH_DTYPES[plan.dtype]
-        self.x = torch.empty((plan.nchans, max_chunk), dtype=tdt, device=plan.device)
-        self.h = torch.empty((plan.nchans, max_chunk), dtype=tdt).pin_memory()
+        # flat buffers: a chunk of L samples is viewed as a contiguous [C][L]
+        # (leading dimension L), so its transfer is one plain copy
+        self.x = torch.empty(plan.nchans * max_chunk, dtype=tdt, device=plan.device)
+        self.h = torch.empty(plan.nchans * max_chunk, dtype=tdt).pin_memory()
         self.state = plan.alloc_rfi_state(max_chunk)
         self.out = plan.alloc_output(max_chunk)
         self.norm = plan.alloc_norm()
@@ -193,9 +196,15 @@ class Server:
             jobs = []
             for r, sl in zip(reqs, slots):
                 Lr = r.data.shape[1]
-                sl.h[:, :Lr].copy_(torch.from_numpy(r.data))
-                x = sl.x[:, :Lr]
-                x.copy_(sl.h[:, :Lr], non_blocking=True)
+                n = plan.nchans * Lr
+                x = sl.x[:n].view(plan.nchans, Lr)
+                if isinstance(r.data, torch.Tensor) and r.data.is_pinned() and r.data.is_contiguous():
+                    x.copy_(r.data, non_blocking=True)
+                else:
+                    src = r.data if isinstance(r.data, torch.Tensor) else torch.from_numpy(r.data)
+                    h = sl.h[:n].view(plan.nchans, Lr)
+                    h.copy_(src)
+                    x.copy_(h, non_blocking=True)
                 st = plan.rfi_threshold(x, sl.state, stream=stream) if self.rfi else None
                 jobs.append(dict(plan=plan, x=x, rfi_state=st, out=sl.out, norm=sl.norm,
                                  beam=self.beams[r.beam_id]))

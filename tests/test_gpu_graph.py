@@ -93,3 +93,54 @@ def test_autotuner_picks_and_caches(tmp_path):
     assert len(cached) == 1
     again = autotune.best_tiling(b.plan_kwargs(), "u8", True, 16384, path=path)
     assert again == r
+
+
+def test_batch_graph_replays_match_eager_batches():
+    """Three uneven beams in one captured step (RFI passes, one persistent
+    launch, detection); every replay equals an eager batched step of a
+    parallel set of beams fed the same chunks."""
+    A = api()
+    shapes = [(256, 48, 11), (384, 64, 12), (512, 80, 13)]     # channels, DMs, seed
+    T = 4096
+    beams, xs = [], []
+    for C, nd, seed in shapes:
+        f0, df = synth.band(C)
+        b = synth.Beam(name=f"bg{C}", nchans=C, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6, ndms=nd,
+                       dm_start=0.0, dm_step=0.2, nsamps=T * 6, dtype="u8", seed=seed,
+                       spikes=[synth.Spike(t0=9000, length=2, amp=20.0)])
+        s = oracle.delay_table(**b.plan_kwargs())
+        b.pulses = [synth.Pulse(dm_index=nd // 2, t0=10000, width=4, amp=1.0)]
+        beams.append(b)
+        xs.append(synth.render(b, s))
+    plans = [A.Plan.from_beam(b, tile_hint=1) for b in beams]
+    assert all(T > p.max_delay for p in plans)
+    gb = [A.Beam(p) for p in plans]           # beams driven by the graph
+    eb = [A.Beam(p) for p in plans]           # beams driven eagerly
+    bufs = [torch.zeros((p.nchans, T), dtype=torch.uint8, device="cuda") for p in plans]
+
+    def eager_step(beam_set, k):
+        jobs = []
+        for p, x, bm in zip(plans, xs, beam_set):
+            xd = torch.from_numpy(np.ascontiguousarray(x[:, k * T:(k + 1) * T])).cuda()
+            jobs.append(dict(plan=p, x=xd, rfi_state=p.rfi_threshold(xd), beam=bm))
+        return A.execute_batch(jobs)
+
+    eager_step(gb, 0)                         # fill the graph beams' rings
+    eager_step(eb, 0)
+    torch.cuda.synchronize()
+    for buf, x in zip(bufs, xs):
+        buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, T:2 * T])))
+    g = A.BatchGraph(plans, bufs, gb, rfi=True, nsigma=6.0)
+    for k in range(1, 5):
+        for buf, x in zip(bufs, xs):          # eager work between replays
+            buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, k * T:(k + 1) * T])))
+        torch.cuda.synchronize()
+        s0 = g.replay()
+        torch.cuda.synchronize()
+        ref = eager_step(eb, k)
+        torch.cuda.synchronize()
+        for i, (out, norm, nout, rs0) in enumerate(ref):
+            assert nout == T and s0[i] == rs0, (k, i)
+            assert torch.equal(g.outs[i][:, :nout], out[:, :nout]), (k, i)
+            assert np.array_equal(A.Plan.norm_to_host(g.norms[i]), A.Plan.norm_to_host(norm)), (k, i)
+        assert [b.position() for b in gb] == [b.position() for b in eb]
