@@ -227,7 +227,9 @@ mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_
  *
  * d_norm (nullable, [ndms]) receives each DM's detrend line and scale over
  * the outputs of this call (Sec. 2.2.3).  info (nullable, host) receives
- * nout and sample0.  ld_out >= nout.  Errors: MB_EINVAL. */
+ * nout and sample0.  d_out must be 16-byte aligned with ld_out >= nout a
+ * multiple of 4, and hold ndms*ld_out floats (the normalisation and
+ * detection read rows in aligned groups of 4).  Errors: MB_EINVAL. */
 mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in,
                          int64_t nsamps, int64_t ld, const void* d_rfi_state,
                          float* d_out, int64_t ld_out, mb_norm* d_norm,

@@ -1,14 +1,18 @@
 // Per-DM detrending and normalisation (Sec. 2.2.3) and the n-sigma event
 // threshold (Sec. 2.3) over a dedispersed plane D[ndms][ld_out] (FP32).
 //
-// norm:   one workgroup per DM row.  Pass 1 forms sum D, sum (t - tbar) D and
-//         sum D^2 in FP64; the least-squares line follows in closed form.
-//         Pass 2 forms the residual sum of squares.  Rows are read twice;
-//         the second read mostly hits the L2 / MALL.
-// detect: pass A counts z > nsigma per (row, quarter-row segment) and finds
-//         the row's peak; a single-workgroup exclusive scan turns counts into
-//         output offsets; pass B rescans only the segments with hits and
-//         writes the triplets in (DM, sample) order with wave ballots.
+// Every kernel here runs one 1024-thread workgroup per DM row, and every
+// row is split into kSeg segments of whole 256-sample groups, one per wave;
+// a lane reads 4 consecutive samples per group with one 16-byte load.
+//
+// norm:   pass 1 forms sum D, sum (t - tbar) D and sum D^2 in FP64; the
+//         least-squares line follows in closed form.  Pass 2 forms the
+//         residual sum of squares.  Rows are read twice; the second read
+//         mostly hits the L2 / MALL.
+// detect: pass A counts z > nsigma per (row, segment) and finds the row's
+//         peak; a single-workgroup exclusive scan turns counts into output
+//         offsets; pass B rescans only the segments with hits and writes the
+//         triplets in (DM, sample) order with a wave prefix sum per group.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -25,18 +29,28 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// 256-thread block sum with a fixed tree; sh must hold 4 doubles.
-__device__ inline double block_sum_256(double v, double* sh) {
+// 1024-thread block sum in a fixed order; sh must hold kSeg doubles.
+__device__ inline double block_sum_1024(double v, double* sh) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < kDetectSegs; ++k) t += sh[k];
+  return t;
 }
 
-__global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out, int64_t ld_out,
-                                                   int64_t nout, NormDev* __restrict__ norm) {
-  __shared__ double sh[4];
+// Segment w of a row of nout samples: whole 256-sample groups.
+__device__ inline void segment(int64_t nout, int w, int64_t& lo, int64_t& hi) {
+  const int64_t seg = ((nout + 256 * kDetectSegs - 1) / (256 * kDetectSegs)) * 256;
+  lo = min(nout, (int64_t)w * seg);
+  hi = min(nout, lo + seg);
+}
+
+__global__ __launch_bounds__(1024) void norm_kernel(const float* __restrict__ out, int64_t ld_out,
+                                                    int64_t nout, NormDev* __restrict__ norm) {
+  __shared__ double sh[kDetectSegs];
   const int d = blockIdx.x;
   const float* row = out + (int64_t)d * ld_out;
   const double N = (double)nout;
@@ -44,7 +58,7 @@ __global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out
   double s1 = 0.0, st = 0.0, s2 = 0.0;
   // 4 samples per thread per step (rows are 16-byte aligned, ld_out % 4 == 0)
   const int64_t n4 = nout / 4;
-  for (int64_t i = threadIdx.x; i < n4; i += 256) {
+  for (int64_t i = threadIdx.x; i < n4; i += 1024) {
     const float4 v = reinterpret_cast<const float4*>(row)[i];
     const double t = (double)(4 * i) - tbar;
     const double a0 = v.x, a1 = v.y, a2 = v.z, a3 = v.w;
@@ -52,18 +66,18 @@ __global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out
     st += (t * a0 + (t + 1.0) * a1) + ((t + 2.0) * a2 + (t + 3.0) * a3);
     s2 += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
   }
-  for (int64_t i = 4 * n4 + threadIdx.x; i < nout; i += 256) {
+  for (int64_t i = 4 * n4 + threadIdx.x; i < nout; i += 1024) {
     const double v = row[i];
     s1 += v; st += ((double)i - tbar) * v; s2 += v * v;
   }
-  s1 = block_sum_256(s1, sh);
-  st = block_sum_256(st, sh);
-  s2 = block_sum_256(s2, sh);
+  s1 = block_sum_1024(s1, sh);
+  st = block_sum_1024(st, sh);
+  s2 = block_sum_1024(s2, sh);
   const double stt = N * (N * N - 1.0) / 12.0;
   const double b = stt > 0.0 ? st / stt : 0.0;
   const double a = (nout > 0 ? s1 / N : 0.0) - b * tbar;
   double r2 = 0.0;
-  for (int64_t i = threadIdx.x; i < n4; i += 256) {
+  for (int64_t i = threadIdx.x; i < n4; i += 1024) {
     const float4 v = reinterpret_cast<const float4*>(row)[i];
     const double t = (double)(4 * i);
     const double r0 = ((double)v.x - a) - b * t;
@@ -72,11 +86,11 @@ __global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out
     const double r3 = ((double)v.w - a) - b * (t + 3.0);
     r2 += (r0 * r0 + r1 * r1) + (rr2 * rr2 + r3 * r3);
   }
-  for (int64_t i = 4 * n4 + threadIdx.x; i < nout; i += 256) {
+  for (int64_t i = 4 * n4 + threadIdx.x; i < nout; i += 1024) {
     const double r = ((double)row[i] - a) - b * (double)i;
     r2 += r * r;
   }
-  r2 = block_sum_256(r2, sh);
+  r2 = block_sum_1024(r2, sh);
   if (threadIdx.x == 0) {
     NormDev nd;
     nd.a = a;
@@ -93,42 +107,50 @@ __global__ __launch_bounds__(256) void norm_kernel(const float* __restrict__ out
 // roundings: r = (D - a) - b t.  z = r / sigma.  The threshold test z > nsigma
 // is taken as r > nsigma * sigma (the same comparison in both passes; it can
 // differ from the quotient only for z within rounding of nsigma).
-__device__ inline double resid(const float* row, int64_t t, const NormDev& n) {
-  return __dsub_rn(__dsub_rn((double)row[t], n.a), __dmul_rn(n.b, (double)t));
+__device__ inline double resid(float v, int64_t t, const NormDev& n) {
+  return __dsub_rn(__dsub_rn((double)v, n.a), __dmul_rn(n.b, (double)t));
 }
 
-// Each row is split into 4 contiguous segments, one per wave of the block;
-// lanes step through a segment 64 samples at a time.
-__device__ inline void wave_segment(int64_t nout, int w, int64_t& lo, int64_t& hi) {
-  const int64_t seg = ((nout + 255) / 256) * 64;      // multiple of 64
-  lo = min(nout, (int64_t)w * seg);
-  hi = min(nout, lo + seg);
+// The 4 samples of a lane at t (a multiple of 4, t < hi): one 16-byte load;
+// rows are ld_out >= nout apart with ld_out % 4 == 0, so it stays in its row.
+__device__ inline float4 quad_at(const float* row, int64_t t) {
+  return *reinterpret_cast<const float4*>(row + t);
 }
 
-// Pass A: hits per (row, wave segment) and the row's peak.
-__global__ __launch_bounds__(256) void detect_count_kernel(const float* __restrict__ out,
-                                                           int64_t ld_out, int64_t nout,
-                                                           const NormDev* __restrict__ norm,
-                                                           double nsigma, int64_t sample0,
-                                                           int64_t* __restrict__ counts,
-                                                           PeakDev* __restrict__ peaks) {
-  __shared__ double shr[4];
-  __shared__ int64_t sht[4];
+// Pass A: hits per (row, segment) and the row's peak.
+__global__ __launch_bounds__(1024) void detect_count_kernel(const float* __restrict__ out,
+                                                            int64_t ld_out, int64_t nout,
+                                                            const NormDev* __restrict__ norm,
+                                                            double nsigma, int64_t sample0,
+                                                            int64_t* __restrict__ counts,
+                                                            PeakDev* __restrict__ peaks) {
+  __shared__ double shr[kDetectSegs];
+  __shared__ int64_t sht[kDetectSegs];
   const int d = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float* row = out + (int64_t)d * ld_out;
   const NormDev n = norm[d];
   const double thr = nsigma * n.sigma;
   int64_t lo, hi;
-  wave_segment(nout, wave, lo, hi);
+  segment(nout, wave, lo, hi);
   int64_t cnt = 0;
   double best = -INFINITY;
   int64_t bt = INT64_MAX;
   if (!n.degenerate) {
-    for (int64_t t = lo + lane; t < hi; t += 64) {
-      const double r = resid(row, t, n);
-      cnt += (r > thr) ? 1 : 0;
-      if (r > best) { best = r; bt = t; }     // ascending t per lane keeps the earliest
+    for (int64_t t0 = lo; t0 < hi; t0 += 256) {
+      const int64_t t = t0 + 4 * lane;
+      if (t < hi) {
+        const float4 q = quad_at(row, t);
+        const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (t + j < hi) {
+            const double r = resid(qv[j], t + j, n);
+            cnt += (r > thr) ? 1 : 0;
+            if (r > best) { best = r; bt = t + j; }   // ascending t per lane keeps the earliest
+          }
+        }
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) {
@@ -138,7 +160,7 @@ __global__ __launch_bounds__(256) void detect_count_kernel(const float* __restri
     if (ob > best || (ob == best && ot < bt)) { best = ob; bt = ot; }
   }
   if (lane == 0) {
-    counts[(int64_t)d * 4 + wave] = cnt;
+    counts[(int64_t)d * kDetectSegs + wave] = cnt;
     shr[wave] = best;
     sht[wave] = bt;
   }
@@ -152,7 +174,7 @@ __global__ __launch_bounds__(256) void detect_count_kernel(const float* __restri
     } else {
       double br = shr[0];
       int64_t btt = sht[0];
-      for (int k = 1; k < 4; ++k)
+      for (int k = 1; k < kDetectSegs; ++k)
         if (shr[k] > br || (shr[k] == br && sht[k] < btt)) { br = shr[k]; btt = sht[k]; }
       p.sample = sample0 + btt;
       p.snr = (float)(br / n.sigma);
@@ -186,21 +208,33 @@ __global__ __launch_bounds__(1024) void detect_scan_kernel(const int64_t* __rest
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Exclusive prefix sum over the 64 lanes of a wave.
+__device__ inline int wave_prefix_excl(int c, int lane, int& total) {
+  int inc = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += o;
+  }
+  total = __shfl(inc, 63, 64);
+  return inc - c;
+}
+
 // Pass B: each wave rescans its segment (only if it holds hits) and writes
-// them in sample order: ballot + popcount within 64 samples, a running
-// offset across them.  No barriers.
-__global__ __launch_bounds__(256) void detect_write_kernel(const float* __restrict__ out,
-                                                           int64_t ld_out, int64_t nout,
-                                                           const NormDev* __restrict__ norm,
-                                                           double nsigma, int64_t sample0,
-                                                           double dm_start, double dm_step,
-                                                           const int64_t* __restrict__ counts,
-                                                           const int64_t* __restrict__ offsets,
-                                                           CandDev* __restrict__ cands,
-                                                           int64_t capacity) {
+// them in sample order: within a 256-sample group, lane-ordered prefix sums
+// of the lanes' hit counts; a running offset across groups.  No barriers.
+__global__ __launch_bounds__(1024) void detect_write_kernel(const float* __restrict__ out,
+                                                            int64_t ld_out, int64_t nout,
+                                                            const NormDev* __restrict__ norm,
+                                                            double nsigma, int64_t sample0,
+                                                            double dm_start, double dm_step,
+                                                            const int64_t* __restrict__ counts,
+                                                            const int64_t* __restrict__ offsets,
+                                                            CandDev* __restrict__ cands,
+                                                            int64_t capacity) {
   const int d = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t slot = (int64_t)d * 4 + wave;
+  const int64_t slot = (int64_t)d * kDetectSegs + wave;
   if (counts[slot] == 0) return;
   int64_t pos = offsets[slot];
   if (pos >= capacity) return;
@@ -209,30 +243,41 @@ __global__ __launch_bounds__(256) void detect_write_kernel(const float* __restri
   const double thr = nsigma * n.sigma;
   const float dmv = (float)(dm_start + (double)d * dm_step);
   int64_t lo, hi;
-  wave_segment(nout, wave, lo, hi);
-  for (int64_t t0 = lo; t0 < hi; t0 += 64) {
-    const int64_t t = t0 + lane;
-    double r = 0.0;
-    bool hit = false;
+  segment(nout, wave, lo, hi);
+  for (int64_t t0 = lo; t0 < hi && pos < capacity; t0 += 256) {
+    const int64_t t = t0 + 4 * lane;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    bool hit[4] = {false, false, false, false};
     if (t < hi) {
-      r = resid(row, t, n);
-      hit = r > thr;
-    }
-    const unsigned long long bal = __ballot(hit);
-    if (hit) {
-      const unsigned long long lower = (lane == 0) ? 0ull : (bal & ((1ull << lane) - 1ull));
-      const int64_t k = pos + __popcll(lower);
-      if (k < capacity) {
-        CandDev cd;
-        cd.dm_index = d;
-        cd.reserved = 0;
-        cd.sample = sample0 + t;
-        cd.snr = (float)(r / n.sigma);
-        cd.dm = dmv;
-        cands[k] = cd;
+      const float4 q = quad_at(row, t);
+      const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (t + j < hi) {
+          r[j] = resid(qv[j], t + j, n);
+          hit[j] = r[j] > thr;
+        }
       }
     }
-    pos += __popcll(bal);
+    const int c = (int)hit[0] + (int)hit[1] + (int)hit[2] + (int)hit[3];
+    int total;
+    int64_t k = pos + wave_prefix_excl(c, lane, total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (hit[j]) {
+        if (k < capacity) {
+          CandDev cd;
+          cd.dm_index = d;
+          cd.reserved = 0;
+          cd.sample = sample0 + t + j;
+          cd.snr = (float)(r[j] / n.sigma);
+          cd.dm = dmv;
+          cands[k] = cd;
+        }
+        ++k;
+      }
+    }
+    pos += total;
   }
 }
 
@@ -240,7 +285,7 @@ __global__ __launch_bounds__(256) void detect_write_kernel(const float* __restri
 
 hipError_t launch_norm(const float* out, int64_t ld_out, int64_t nout, int32_t ndms, NormDev* norm,
                        hipStream_t s) {
-  hipLaunchKernelGGL(norm_kernel, dim3((unsigned)ndms), dim3(256), 0, s, out, ld_out, nout, norm);
+  hipLaunchKernelGGL(norm_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout, norm);
   return hipGetLastError();
 }
 
@@ -249,12 +294,12 @@ hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t
                          double dm_step, CandDev* cands, int64_t capacity, int64_t* d_count,
                          PeakDev* peaks, void* work, hipStream_t s) {
   int64_t* counts = static_cast<int64_t*>(work);
-  int64_t* offsets = counts + 4 * (int64_t)ndms;
-  hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)ndms), dim3(256), 0, s, out, ld_out, nout,
+  int64_t* offsets = counts + kDetectSegs * (int64_t)ndms;
+  hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout,
                      norm, nsigma, sample0, counts, peaks);
-  hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(1024), 0, s, counts, 4 * (int64_t)ndms,
-                     offsets, d_count);
-  hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)ndms), dim3(256), 0, s, out, ld_out, nout,
+  hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(1024), 0, s, counts,
+                     kDetectSegs * (int64_t)ndms, offsets, d_count);
+  hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout,
                      norm, nsigma, sample0, dm_start, dm_step, counts, offsets, cands, capacity);
   return hipGetLastError();
 }

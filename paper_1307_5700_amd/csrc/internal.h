@@ -194,8 +194,12 @@ hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t
                          double dm_start, double dm_step, CandDev* cands, int64_t capacity,
                          int64_t* d_count, PeakDev* peaks, void* work, hipStream_t s);
 
+// Segments (one wave each) per DM row in the detection kernels.
+constexpr int kDetectSegs = 16;
+
 inline size_t detect_work_bytes(int32_t ndms) {
-  return align256(sizeof(int64_t) * 8 * size_t(ndms));   // counts and offsets per (row, segment)
+  // counts and offsets per (row, segment)
+  return align256(sizeof(int64_t) * 2 * kDetectSegs * size_t(ndms));
 }
 
 }  // namespace mbtp

@@ -138,10 +138,13 @@ __global__ __launch_bounds__(256) void rfi_chunks_kernel(const double* __restric
 // ---------------------------------------------------------------------------
 constexpr int kMaxP = 8;
 
-__device__ inline void legendre(double u, int p, double* P) {
+// Legendre polynomials P_0..P_D at u (three-term recurrence), unrolled.
+template <int D>
+__device__ inline void legendre(double u, double (&P)[D + 1]) {
   P[0] = 1.0;
-  if (p >= 1) P[1] = u;
-  for (int k = 1; k < p; ++k) P[k + 1] = ((2 * k + 1) * u * P[k] - k * P[k - 1]) / (k + 1);
+  if constexpr (D >= 1) P[1] = u;
+#pragma unroll
+  for (int k = 1; k < D; ++k) P[k + 1] = ((2 * k + 1) * u * P[k] - k * P[k - 1]) / (k + 1);
 }
 
 __device__ inline double u_of(int64_t c, int64_t C) {
@@ -172,72 +175,97 @@ __device__ inline void block_sums_1024(const double (&v)[NV], double* sh /* 16*N
   for (int k = 0; k < NV; ++k) out[k] = sh[16 * NV + k];
 }
 
-constexpr int kNG = (kMaxP + 1) * (kMaxP + 2) / 2;   // packed lower Gram entries
+// Packed lower-triangular index of (i, j), j <= i.
+constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // Cholesky factor (packed lower, in L) of the Legendre Gram matrix of degree
-// p over the C channel positions.  All threads call it.
-__device__ void gram_cholesky(int64_t C, int p, double* sh, double* L) {
-  const int n = p + 1;
-  double Gl[kNG];
-  for (int i = 0; i < kNG; ++i) Gl[i] = 0.0;
-  double P[kMaxP + 1];
+// D over the C channel positions.  All threads call it; every array has a
+// compile-time size, so nothing leaves registers.
+template <int D>
+__device__ void gram_cholesky(int64_t C, double* sh, double* L) {
+  constexpr int N = D + 1, NG = N * (N + 1) / 2;
+  double Gl[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) Gl[i] = 0.0;
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
-    legendre(u_of(c, C), p, P);
-    int k = 0;
-    for (int i = 0; i <= kMaxP; ++i)
-      for (int j = 0; j <= i; ++j, ++k)
-        if (i < n) Gl[k] += P[i] * P[j];
+    double P[N];
+    legendre<D>(u_of(c, C), P);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) Gl[tri(i, j)] += P[i] * P[j];
   }
-  double G[kNG];
-  block_sums_1024<kNG>(Gl, sh, G);
+  double G[NG];
+  block_sums_1024<NG>(Gl, sh, G);
   if (threadIdx.x == 0) {
-    for (int i = 0; i < n; ++i) {
+    double Lr[NG];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
       for (int j = 0; j <= i; ++j) {
-        double s = G[i * (i + 1) / 2 + j];
-        for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-        if (i == j) L[i * (i + 1) / 2 + i] = sqrt(s > 0.0 ? s : 0.0);
-        else L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+        double v = G[tri(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= Lr[tri(i, k)] * Lr[tri(j, k)];
+        if (i == j) Lr[tri(i, i)] = sqrt(v > 0.0 ? v : 0.0);
+        else Lr[tri(i, j)] = v / Lr[tri(j, j)];
       }
-    }
+#pragma unroll
+    for (int i = 0; i < NG; ++i) L[i] = Lr[i];
   }
   __syncthreads();
 }
 
 // Least-squares fit of v[c] with the factored Gram matrix: writes the fitted
 // curve to fit[c] and returns the RMSE of v - fit.  All threads call it.
-__device__ double fit_poly(const double* v, int64_t C, int p, const double* L, double* fit,
-                           double* sh, double* coef_sh) {
-  const int n = p + 1;
-  double hl[kMaxP + 1];
-  for (int i = 0; i <= kMaxP; ++i) hl[i] = 0.0;
-  double P[kMaxP + 1];
+template <int D>
+__device__ double fit_poly(const double* v, int64_t C, const double* L, double* fit, double* sh,
+                           double* coef_sh) {
+  constexpr int N = D + 1;
+  double hl[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) hl[i] = 0.0;
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
-    legendre(u_of(c, C), p, P);
+    double P[N];
+    legendre<D>(u_of(c, C), P);
     const double vc = v[c];
-    for (int i = 0; i <= kMaxP; ++i)
-      if (i < n) hl[i] += P[i] * vc;
+#pragma unroll
+    for (int i = 0; i < N; ++i) hl[i] += P[i] * vc;
   }
-  double h[kMaxP + 1];
-  block_sums_1024<kMaxP + 1>(hl, sh, h);
+  double h[N];
+  block_sums_1024<N>(hl, sh, h);
   if (threadIdx.x == 0) {
-    double y[kMaxP + 1];
-    for (int i = 0; i < n; ++i) {
-      double s = h[i];
-      for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * y[k];
-      y[i] = s / L[i * (i + 1) / 2 + i];
+    double Lr[N * (N + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < N * (N + 1) / 2; ++i) Lr[i] = L[i];
+    double y[N], x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {            // L y = h
+      double t = h[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= Lr[tri(i, k)] * y[k];
+      y[i] = t / Lr[tri(i, i)];
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = y[i];
-      for (int k = i + 1; k < n; ++k) s -= L[k * (k + 1) / 2 + i] * coef_sh[k];
-      coef_sh[i] = s / L[i * (i + 1) / 2 + i];
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {       // L^T x = y
+      double t = y[i];
+#pragma unroll
+      for (int k = i + 1; k < N; ++k) t -= Lr[tri(k, i)] * x[k];
+      x[i] = t / Lr[tri(i, i)];
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i) coef_sh[i] = x[i];
   }
   __syncthreads();
+  double coef[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) coef[i] = coef_sh[i];
   double ssq[1] = {0.0};
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
-    legendre(u_of(c, C), p, P);
+    double P[N];
+    legendre<D>(u_of(c, C), P);
     double f = 0.0;
-    for (int i = 0; i < n; ++i) f += coef_sh[i] * P[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) f += coef[i] * P[i];
     fit[c] = f;
     const double r = v[c] - f;
     ssq[0] += r * r;
@@ -247,6 +275,7 @@ __device__ double fit_poly(const double* v, int64_t C, int p, const double* L, d
   return sqrt(tot[0] / (double)C);
 }
 
+template <int D>
 __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, RfiParamsDev prm,
                                                        const double* __restrict__ bsum,
                                                        double* __restrict__ binterp,
@@ -254,32 +283,30 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
                                                        float* __restrict__ fit32,
                                                        uint8_t* __restrict__ masked,
                                                        RfiHeader* __restrict__ hdr) {
-  __shared__ double sh[17 * kNG];
-  __shared__ double coef_sh[kMaxP + 1];
-  __shared__ double L[kNG];
-  __shared__ int any_left;
+  constexpr int NG = (D + 1) * (D + 2) / 2;
+  __shared__ double sh[17 * NG + 17];
+  __shared__ double coef_sh[D + 1];
+  __shared__ double L[NG];
   const double invT = 1.0 / (double)T;
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     binterp[c] = bsum[c] * invT;
     masked[c] = 0;
   }
-  gram_cholesky(C, prm.p, sh, L);   // (its barriers also publish binterp/masked)
+  gram_cholesky<D>(C, sh, L);   // (its barriers also publish binterp/masked)
   double rmse0 = 0.0;
-  int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
+  int any_left = 1;
+  const int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
   for (int pass = 0; pass < passes; ++pass) {
-    const double rmse_i = fit_poly(binterp, C, prm.p, L, fit, sh, coef_sh);
+    const double rmse_i = fit_poly<D>(binterp, C, L, fit, sh, coef_sh);
     if (pass == 0) rmse0 = rmse_i;
     const double thr = prm.k_mask * rmse_i;
+    int left = 0;
     for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
       const double r = bsum[c] * invT - fit[c];
       if (fabs(r) > thr) masked[c] = 1;
+      left |= masked[c] ? 0 : 1;
     }
-    if (threadIdx.x == 0) any_left = 0;
-    __syncthreads();
-    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
-      if (!masked[c]) atomicOr(&any_left, 1);
-    }
-    __syncthreads();
+    any_left = __syncthreads_or(left);       // also publishes masked[]
     if (!any_left) break;
     // nearest unmasked neighbour on each side (one side at a band edge)
     for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
@@ -308,7 +335,7 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
     }
     return;
   }
-  const double rmse = fit_poly(binterp, C, prm.p, L, fit, sh, coef_sh);
+  const double rmse = fit_poly<D>(binterp, C, L, fit, sh, coef_sh);
   double sums[2] = {0.0, 0.0};
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     fit32[c] = (float)fit[c];
@@ -496,8 +523,15 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
                      dim3(256), 0, s, x, ld, g.C, g.T, g.nspans, g.CG, span_sum, spart);
   hipLaunchKernelGGL(rfi_chunks_kernel, dim3((unsigned)((g.C + 3) / 4)), dim3(256), 0, s,
                      span_sum, g.C, g.nspans, g.W / kSpan, g.J, chunk, bsum);
-  hipLaunchKernelGGL(rfi_fit_kernel, dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, binterp,
-                     fit, fit32, masked, hdr);
+  switch (prm.p) {
+#define MBTP_FIT(D_) \
+    case D_: hipLaunchKernelGGL(rfi_fit_kernel<D_>, dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, \
+                                binterp, fit, fit32, masked, hdr); break;
+    MBTP_FIT(0) MBTP_FIT(1) MBTP_FIT(2) MBTP_FIT(3) MBTP_FIT(4) MBTP_FIT(5) MBTP_FIT(6)
+    MBTP_FIT(7) MBTP_FIT(8)
+#undef MBTP_FIT
+    default: return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(rfi_chunk_flags_kernel, dim3((unsigned)g.J), dim3(256), 0, s, chunk, fit,
                      g.C, g.T, g.W, g.J, hdr, flags, lcount, list);
   hipLaunchKernelGGL(rfi_spectrum_flags_kernel<TIN>, dim3((unsigned)((g.T + 255) / 256)),
