@@ -136,8 +136,8 @@ def main():
         traffic_summary(*args.traffic_from)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the design notes describe how it would shard by beam, DM or time)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (sharding by beam, "
+              "DM range or time span is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
