@@ -190,21 +190,31 @@ template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int
 __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* __restrict__ relb,
                                             const float* __restrict__ fit32, float* lds,
                                             int dblock, int ttile) {
-  constexpr int NT = 64 * NW, BD = NW * G, BT = 256 * Q;
-  // staging: NW >= BC: WPR waves share a row and split its quads (each a
-  // contiguous range, one quad of overlap); NW < BC: each wave stages RPW
+  // P bit 3: warp specialisation.  The first kProducers waves only stage
+  // (producers), the others only accumulate (consumers), each role in its
+  // own loop with one barrier per channel block, so staging of block k+1
+  // overlaps the accumulation of block k and neither role holds the other's
+  // registers.  Otherwise every wave stages and accumulates.
+  constexpr bool WS = (P & 8) != 0;
+  constexpr int kProducers = 4;
+  constexpr int NSW = WS ? kProducers : NW;        // staging waves
+  constexpr int NAW = WS ? NW - kProducers : NW;   // accumulating waves
+  constexpr int BD = NAW * G, BT = 256 * Q;
+  // staging: NSW >= BC: WPR waves share a row and split its quads (each a
+  // contiguous range, one quad of overlap); NSW < BC: each wave stages RPW
   // whole rows.  KM quads per lane and row cover rows of up to
   // 64*kStageQuads quads.
-  constexpr int WPR = NW >= BC ? NW / BC : 1;
-  constexpr int RPW = NW >= BC ? 1 : BC / NW;
+  constexpr int WPR = NSW >= BC ? NSW / BC : 1;
+  constexpr int RPW = NSW >= BC ? 1 : BC / NSW;
   constexpr int QWMAX = (64 * kStageQuads - 1 + WPR - 1) / WPR + 1;
   constexpr int KM = RPW > 1 ? kStageQuads / RPW : (QWMAX + 63) / 64;
-  static_assert((G == 2 || G % 4 == 0) && (NW >= BC ? NW % BC == 0 : BC % NW == 0) &&
-                (RPW == 1 || RPW * KM == kStageQuads) && BD * BC <= NT && kAccGroup % BC == 0,
-                "tiling");
+  static_assert((G == 2 || G % 4 == 0) && (NSW >= BC ? NSW % BC == 0 : BC % NSW == 0) &&
+                (RPW == 1 || RPW * KM == kStageQuads) && BD * BC <= 64 * NSW &&
+                kAccGroup % BC == 0 && (!WS || ((P & 2) != 0 && NAW > 0)), "tiling");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
+  const int aw = WS ? wave - kProducers : wave;     // accumulating wave index
 
   const int C = A.C;
   const int d0 = dblock * BD;
@@ -230,21 +240,25 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   auto stage_rows = [&](int b) { return lds + b * stage_floats; };
   auto stage_off = [&](int b) { return reinterpret_cast<int*>(lds + b * stage_floats + BC * 4 * RS); };
 
-  auto row_of = [&](int rr) { return NW >= BC ? wave / WPR : wave + NW * rr; };
+  auto row_of = [&](int rr) { return NSW >= BC ? wave / WPR : wave + NSW * rr; };
   // this wave's quads of its row(s): [m0, mend); the last quad of a range
   // that is not the row's last is written by the next wave as well, which
   // alone has its successor quad and so writes its shifted copies
-  const int wr = NW >= BC ? wave % WPR : 0;
+  const int wr = NSW >= BC ? wave % WPR : 0;
   const int qw = WPR > 1 ? (RS4 - 1 + WPR - 1) / WPR + 1 : RS4;
   const int m0 = wr * (qw - 1);
   const int mend = min(m0 + qw, RS4);
 
-  Staged<TIN, RING> st[RPW][KM];
-  RowMeta rm[RPW];
+  // Staging state of a block in flight.  Producers with a prefetch depth of
+  // two (P bit 4) keep two sets, used alternately; otherwise set 0.
+  constexpr bool PF2 = WS && (P & 16) != 0;
+  constexpr int NSET = PF2 ? 2 : 1;
+  Staged<TIN, RING> st[NSET][RPW][KM];
+  RowMeta rm[NSET][RPW];
   int basen[RPW];        // s[d0][c] of the row in the block after next (vector load, lands early)
-  float fitn[RPW];       // bandpass value of the row being staged (loaded with its quads)
-  int32_t rowt[RPW];     // chunk index of the staged row's window start (uniform)
-  int offreg = 0;
+  float fitn[NSET][RPW]; // bandpass value of the row being staged (loaded with its quads)
+  int32_t rowt[NSET][RPW]; // chunk index of the staged row's window start (uniform)
+  int offreg[NSET] = {};
 
   // Cleaning metadata of row c (vector loads: they count on vmcnt only, so
   // nothing scalar is pending while LDS reads are in flight).
@@ -265,7 +279,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     }
   };
 
-  auto issue_block = [&](int cb0) {
+  auto issue_block = [&](int cb0, auto set_c) {
+    constexpr int S = decltype(set_c)::value;
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       const int c = cb0 + row_of(rr);
@@ -273,15 +288,15 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         const int base = __builtin_amdgcn_readfirstlane(basen[rr]);
         const int64_t a = t0 + (base & ~3);
         const int32_t aw = (int32_t)(a - vring);     // chunk index of the window start
-        rowt[rr] = aw;
+        rowt[S][rr] = aw;
         const TIN* xrow = static_cast<const TIN*>(A.x) + (int64_t)c * A.ld;
         const float* ringrow = RING ? A.ring + (int64_t)c * A.R : nullptr;
-        load_meta(rm[rr], c, a);
-        if (CLEAN) fitn[rr] = fit32[c + lane * A.zero];
+        load_meta(rm[S][rr], c, a);
+        if (CLEAN) fitn[S][rr] = fit32[c + lane * A.zero];
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           const int m = m0 + lane + 64 * k;
-          issue<TIN, CLEAN, RING>(st[rr][k], A, xrow, ringrow, aw + 4 * m, m < mend, pv);
+          issue<TIN, CLEAN, RING>(st[S][rr][k], A, xrow, ringrow, aw + 4 * m, m < mend, pv);
         }
       }
       const int cn = cb0 + BC + row_of(rr);
@@ -293,7 +308,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       const int dd = tid % BD, cb = min(tid / BD, BC - 1);
       const int d = min(d0 + dd, dlast);
       const int cc = min(cb0 + cb, C - 1);
-      offreg = relb[(int64_t)d * A.relb_ld + cc];
+      offreg[S] = relb[(int64_t)d * A.relb_ld + cc];
     }
   };
 
@@ -301,7 +316,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // lane's quad is the next lane's (a DPP wave shift); lane 63 takes lane 0's
   // quad of the next k.  The last quad of a row has no successor in
   // registers, but no DM window reads the copy positions it would feed.
-  auto write_block = [&](int cb0, int buf) {
+  auto write_block = [&](int cb0, int buf, auto set_c) {
+    constexpr int S = decltype(set_c)::value;
     float* const rows = stage_rows(buf);
     int* const lds_off = stage_off(buf);
 #pragma unroll
@@ -315,32 +331,32 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         for (int m = m0 + lane; m < mend; m += 64)
           *reinterpret_cast<float4*>(row + 4 * m) = make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
-        const float fit = CLEAN ? fitn[rr] : 0.0f;
+        const float fit = CLEAN ? fitn[S][rr] : 0.0f;
         float4 lo[KM];
         // Fast path (uniform per row): the wave's quads all lie inside the
         // chunk and none of their chunks or spectra is flagged, so a quad
         // needs only widening and the bandpass subtraction.
-        const int32_t t_lo = rowt[rr] + 4 * m0, t_hi = rowt[rr] + 4 * mend;
+        const int32_t t_lo = rowt[S][rr] + 4 * m0, t_hi = rowt[S][rr] + 4 * mend;
         bool fast = t_lo >= 0 && t_hi <= (int32_t)A.L;
         if (CLEAN) {
           uint32_t gor = 0;
 #pragma unroll
-          for (int k = 0; k < KM; ++k) gor |= st[rr][k].g;
-          const uint32_t mbits = __builtin_amdgcn_readfirstlane(rm[rr].m_lo | rm[rr].m_hi);
+          for (int k = 0; k < KM; ++k) gor |= st[S][rr][k].g;
+          const uint32_t mbits = __builtin_amdgcn_readfirstlane(rm[S][rr].m_lo | rm[S][rr].m_hi);
           fast = fast && mbits == 0 && __builtin_amdgcn_ballot_w64(gor != 0) == 0;
         }
         if (fast) {
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
             float4 f;
-            if constexpr (std::is_same<TIN, float>::value) f = st[rr][k].raw;
-            else f = Quad<TIN>::widen(st[rr][k].raw);
+            if constexpr (std::is_same<TIN, float>::value) f = st[S][rr][k].raw;
+            else f = Quad<TIN>::widen(st[S][rr][k].raw);
             if (CLEAN) { f.x -= fit; f.y -= fit; f.z -= fit; f.w -= fit; }
             lo[k] = f;
           }
         } else {
 #pragma unroll
-          for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[rr][k], A, rm[rr], fit);
+          for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit);
         }
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
@@ -370,7 +386,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         }
       }
     }
-    if (tid < BD * BC) lds_off[tid] = (cb0 + tid / BD < C) ? offreg : 0;   // [cb][dd], dd fastest
+    if (tid < BD * BC) lds_off[tid] = (cb0 + tid / BD < C) ? offreg[S] : 0;   // [cb][dd], dd fastest
   };
 
   float4 acc[G][Q], tot[G][Q];
@@ -392,33 +408,53 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // written into the other stage while block k is accumulated (its loads
   // were issued one block earlier), then the loads of block k+2 are issued;
   // one barrier per block.
-  issue_block(0);
-  write_block(0, 0);
-  if (DB && BC < C) issue_block(BC);
-  __syncthreads();
-  int cur = 0;
-  for (int cb0 = 0; cb0 < C; cb0 += BC) {
-    const int next = cb0 + BC;
-    if constexpr (DB) {
-      if (next < C) {
-        write_block(next, cur ^ 1);
-        if (next + BC < C) issue_block(next + BC);
-      }
-    } else {
-      if (next < C) issue_block(next);
-    }
+  // Accumulates channel block cb0 from LDS stage cur into acc (and tot at
+  // every kAccGroup-th channel).
+  auto accumulate = [&](int cb0, int cur) {
     // ---- accumulate channel block cb0 ----
     // Straight-line over the BC channels (rows past C are zeros).
     const char* base = reinterpret_cast<const char*>(stage_rows(cur)) + 16 * lane;
     const int* lds_off = stage_off(cur);
-    if constexpr ((P & 1) == 0) {
+    if constexpr ((P & 4) != 0) {
+      // pipelined: two register sets; the reads of channel cb+1 and the
+      // offsets of channel cb+2 are issued before the adds of channel cb
+      // (for tilings whose occupancy does not drop with the extra registers)
+      int off[2][G];
+      float4 v[2][G][Q];
+      load_offsets(lds_off + 0 * BD + aw * G, off[0]);
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[0][g][q] = reinterpret_cast<const float4*>(base + off[0][g])[64 * q];
+      if (BC > 1) load_offsets(lds_off + 1 * BD + aw * G, off[1]);
+#pragma unroll
+      for (int cb = 0; cb < BC; ++cb) {
+        if (cb + 1 < BC) {
+          const char* rowb = base + (cb + 1) * 16 * RS;
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+              v[(cb + 1) & 1][g][q] = reinterpret_cast<const float4*>(rowb + off[(cb + 1) & 1][g])[64 * q];
+        }
+        if (cb + 2 < BC) load_offsets(lds_off + (cb + 2) * BD + aw * G, off[cb & 1]);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const float4 w = v[cb & 1][g][q];
+            acc[g][q].x += w.x; acc[g][q].y += w.y;
+            acc[g][q].z += w.z; acc[g][q].w += w.w;
+          }
+      }
+    } else if constexpr ((P & 1) == 0) {
       // serial: per channel the offsets, then its G*Q reads, then the adds;
       // latency is hidden by the other resident waves
 #pragma unroll
       for (int cb = 0; cb < BC; ++cb) {
         const char* rowb = base + cb * 16 * RS;
         int off[G];
-        load_offsets(lds_off + cb * BD + wave * G, off);
+        load_offsets(lds_off + cb * BD + aw * G, off);
         float4 v[G][Q];
 #pragma unroll
         for (int g = 0; g < G; ++g)
@@ -440,7 +476,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       int off[BC][G];
 #pragma unroll
       for (int cb = 0; cb < BC; ++cb) {
-        load_offsets(lds_off + cb * BD + wave * G, off[cb]);
+        load_offsets(lds_off + cb * BD + aw * G, off[cb]);
 #pragma unroll
         for (int g = 0; g < G; ++g) off[cb][g] = __builtin_amdgcn_readfirstlane(off[cb][g]);
       }
@@ -477,12 +513,85 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           acc[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
-    __syncthreads();
-    if constexpr (DB) {
-      cur ^= 1;
-    } else if (next < C) {
-      write_block(next, 0);
+  };
+
+  // Single buffer: per block, issue the loads of block k+1, accumulate block
+  // k, barrier, write block k+1, barrier.  Double buffer: block k+1 is
+  // written into the other stage while block k is accumulated (its loads
+  // were issued one block earlier), then the loads of block k+2 are issued;
+  // one barrier per block.  Warp-specialised: the same double-buffered
+  // schedule, producers and consumers in separate loops that execute the same
+  // number of barriers (one before the loop, one per block).
+  const bool stager = !WS || wave < kProducers;
+  using Set0 = std::integral_constant<int, 0>;
+  using SetL = std::integral_constant<int, NSET - 1>;   // second set (or set 0)
+  if (stager) {
+    issue_block(0, Set0{});
+    write_block(0, 0, Set0{});
+    if (DB && BC < C) issue_block(BC, Set0{});
+    if (PF2 && 2 * BC < C) issue_block(2 * BC, SetL{});
+  }
+  __syncthreads();
+  if constexpr (WS) {
+    if (stager) {
+      if constexpr (PF2) {
+        // block k+1 sits in set k & 1: two steps per iteration keep the set
+        // indices compile-time; each step writes block k+1, issues block
+        // k+3 into the set it freed, and ends with the block's barrier
+        int cur = 0;
+        auto step = [&](int cb0, auto set_c) {
+          const int next = cb0 + BC;
+          if (next < C) {
+            write_block(next, cur ^ 1, set_c);
+            if (next + 2 * BC < C) issue_block(next + 2 * BC, set_c);
+          }
+          __syncthreads();
+          cur ^= 1;
+        };
+        for (int cb0 = 0; cb0 < C; cb0 += 2 * BC) {
+          step(cb0, Set0{});
+          if (cb0 + BC < C) step(cb0 + BC, SetL{});
+        }
+      } else {
+        int cur = 0;
+        for (int cb0 = 0; cb0 < C; cb0 += BC) {
+          const int next = cb0 + BC;
+          if (next < C) {
+            write_block(next, cur ^ 1, Set0{});
+            if (next + BC < C) issue_block(next + BC, Set0{});
+          }
+          __syncthreads();
+          cur ^= 1;
+        }
+      }
+      return;                   // producers hold no outputs
+    }
+    int cur = 0;
+    for (int cb0 = 0; cb0 < C; cb0 += BC) {
+      accumulate(cb0, cur);
       __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    int cur = 0;
+    for (int cb0 = 0; cb0 < C; cb0 += BC) {
+      const int next = cb0 + BC;
+      if constexpr (DB) {
+        if (next < C) {
+          write_block(next, cur ^ 1, Set0{});
+          if (next + BC < C) issue_block(next + BC, Set0{});
+        }
+      } else {
+        if (next < C) issue_block(next, Set0{});
+      }
+      accumulate(cb0, cur);
+      __syncthreads();
+      if constexpr (DB) {
+        cur ^= 1;
+      } else if (next < C) {
+        write_block(next, 0, Set0{});
+        __syncthreads();
+      }
     }
   }
   if ((C & (kAccGroup - 1)) != 0) {
@@ -497,7 +606,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // ---- store: output j sits at virtual index phase + j ----
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int d = d0 + wave * G + g;
+    const int d = d0 + aw * G + g;
     if (d > dlast) continue;
     float* orow = A.out + (int64_t)d * A.ld_out;
 #pragma unroll
@@ -608,12 +717,14 @@ hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit
 
 // Compiled tilings: (waves per workgroup, DMs per wave, float4 groups per
 // lane, channels per LDS stage, P: bit 0 rolling accumulation, bit 1 double-
-// buffered LDS stages).
+// buffered LDS stages, bit 2 pipelined accumulation with two register sets,
+// bit 3 warp specialisation: four producer waves, the rest consumers, bit 4
+// with bit 3: producers keep two blocks of loads in flight).
 // The plan takes the first that fits its LDS and staging limits: the last
-// three, with 16 and 8 DMs per block, serve DM grids whose delay spread per
+// four, with 16 and 8 DMs per block, serve DM grids whose delay spread per
 // DM step is large (coarse steps, slow sampling).
-#define MBTP_TILINGS(X) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(16, 2, 2, 4, 2) X(8, 4, 2, 8, 1) \
-  X(8, 4, 2, 4, 2) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0)
+#define MBTP_TILINGS(X) X(12, 4, 2, 4, 10) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(8, 4, 2, 4, 2) \
+  X(12, 2, 2, 4, 10) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,

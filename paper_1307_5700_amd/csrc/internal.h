@@ -146,7 +146,8 @@ struct Tiling {
   int NW, G, Q, BC;   // waves per workgroup, DMs per wave, float4 groups per lane,
                       // channels per LDS stage
   int P;              // bit 0: rolling accumulation loop; bit 1: two LDS stages
-  int BD() const { return NW * G; }
+  int staging_waves() const { return (P & 8) ? 4 : NW; }           // P bit 3: 4 producers
+  int BD() const { return ((P & 8) ? NW - 4 : NW) * G; }            // consumers x G
   int BT() const { return 256 * Q; }
   int threads() const { return 64 * NW; }
 };

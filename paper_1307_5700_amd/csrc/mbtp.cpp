@@ -140,20 +140,22 @@ void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
 
 // A tiling fits when its LDS fits and each lane's prefetch registers cover
 // its share of a channel block.
-// Staging registers: with NW >= BC, WPR waves split a row of rs/4 quads into
-// ranges of qw quads (one quad of overlap) and each lane holds KM of them;
-// with NW < BC a wave stages BC/NW whole rows.  Same rule as the kernel.
+// Staging registers: with NSW >= BC staging waves, WPR waves split a row of
+// rs/4 quads into ranges of qw quads (one quad of overlap) and each lane
+// holds KM of them; with NSW < BC a wave stages BC/NSW whole rows.  Same
+// rule as the kernel.
 bool tiling_fits(const Tiling& t, int rs, size_t lds) {
   const int rs4 = rs / 4;
   if (lds > kMaxLds) return false;
-  if (t.NW >= t.BC) {
-    const int wpr = t.NW / t.BC;
+  const int nsw = t.staging_waves();
+  if (nsw >= t.BC) {
+    const int wpr = nsw / t.BC;
     const int qwmax = (64 * kStageQuads - 1 + wpr - 1) / wpr + 1;
     const int km = (qwmax + 63) / 64;
     const int qw = wpr > 1 ? (rs4 - 1 + wpr - 1) / wpr + 1 : rs4;
     return qw <= 64 * km;
   }
-  const int rows_per_wave = t.BC / t.NW;
+  const int rows_per_wave = t.BC / nsw;
   return rows_per_wave * ((rs4 + 63) / 64) <= kStageQuads;
 }
 
