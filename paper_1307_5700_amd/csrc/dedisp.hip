@@ -69,12 +69,12 @@ template <> struct Quad<uint8_t> {
 // prefetch of the next channel block with the accumulation of this one.
 // Which samples of the quad are valid, whether it comes from the ring, and
 // the cleaning are all applied with selects when the quad is written to LDS.
+// The quad's chunk index is not kept: it follows from the row's (uniform)
+// window start and the lane's quad number when the quad is written.
 template <typename TIN, bool RING> struct Staged {
   typename Quad<TIN>::Raw raw;       // chunk values (f32: chunk or ring values)
   float4 rv;                         // ring values (u8 / f16 with a ring only)
   uint32_t g;                        // spectrum flags of the 4 samples (cleaning)
-  int32_t t;                         // chunk index of the first sample: < 0 ring,
-                                     // >= L (or kNoQuad) nothing to stage
 };
 constexpr int32_t kNoQuad = 0x3fffffff;
 
@@ -121,24 +121,25 @@ __device__ inline void issue(Staged<TIN, RING>& s, const DedispArgs& A, const TI
       else
         s.rv = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    s.t = !live ? kNoQuad : (in_ring ? -1 : min(t, kNoQuad));
   } else {
     s.raw = Quad<TIN>::load(xrow + off);
-    s.t = (live && t < L) ? t : kNoQuad;
   }
 }
 
 // Widens and cleans a landed quad: samples past the chunk end are 0; ring
 // samples were cleaned when they entered the ring.  Chunk flags come from
 // the row's 64-bit mask, spectrum flags from the word loaded with the quad.
+// tq: chunk index of the quad's first sample (as issued); live: the lane's
+// quad is in its range.
 template <typename TIN, bool CLEAN, bool RING>
 __device__ inline float4 finish(const Staged<TIN, RING>& s, const DedispArgs& A, const RowMeta& rm,
-                                float fit) {
+                                float fit, int32_t tq, bool live) {
   float4 f;
   if constexpr (std::is_same<TIN, float>::value) f = s.raw;
   else f = Quad<TIN>::widen(s.raw);
-  const int32_t t = s.t;
   const int32_t L = (int32_t)A.L;                            // <= 2^30: 32-bit compares
+  // < 0: ring quad; >= L (kNoQuad): nothing to stage
+  const int32_t t = !live ? kNoQuad : (RING && tq < 0 ? -1 : (tq < L ? tq : kNoQuad));
   const bool ring = RING && t < 0;
   const int32_t tc = (uint32_t)t < (uint32_t)L ? t : 0;      // in-range stand-in for the chunk index
   const int32_t left = L - t;                                // valid samples from t on
@@ -184,6 +185,113 @@ __device__ inline void load_offsets(const int* src, int (&o)[G]) {
   }
 }
 
+// acc[q] += the 4 window samples that start r (uniform, 0..3) samples into
+// the lane's aligned quad v[q]; the samples past the quad are the next
+// lane's, taken by a DPP wave shift fused into the add (lane 63 adds 0).
+// One block of code per residue, chosen by scalar branches: the adds of the
+// cases must not be merged behind the branch (the compiler would then keep
+// every routed value live in registers), and the accumulators stay in the
+// same registers whatever the residue.  The s_nop covers the wait a DPP
+// source needs after a VALU write.
+template <int Q>
+__device__ inline void add_shifted(float4 (&acc)[Q], const float4 (&v)[Q], int r);
+
+template <>
+__device__ inline void add_shifted<1>(float4 (&acc)[1], const float4 (&v)[1], int r) {
+  asm(
+      "s_cmp_eq_u32 %8, 0\n\t"
+      "s_cbranch_scc1 .Lr0_%=\n\t"
+      "s_cmp_eq_u32 %8, 1\n\t"
+      "s_cbranch_scc1 .Lr1_%=\n\t"
+      "s_cmp_eq_u32 %8, 2\n\t"
+      "s_cbranch_scc1 .Lr2_%=\n\t"
+      "v_add_f32 %0, %7, %0\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %1, %4, %1 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %2, %5, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %6, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr0_%=:\n\t"
+      "v_add_f32 %0, %4, %0\n\t"
+      "v_add_f32 %1, %5, %1\n\t"
+      "v_add_f32 %2, %6, %2\n\t"
+      "v_add_f32 %3, %7, %3\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr1_%=:\n\t"
+      "v_add_f32 %0, %5, %0\n\t"
+      "v_add_f32 %1, %6, %1\n\t"
+      "v_add_f32 %2, %7, %2\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %3, %4, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr2_%=:\n\t"
+      "v_add_f32 %0, %6, %0\n\t"
+      "v_add_f32 %1, %7, %1\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %2, %4, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %5, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      ".Lend_%=:"
+      : "+v"(acc[0].x), "+v"(acc[0].y), "+v"(acc[0].z), "+v"(acc[0].w)
+      : "v"(v[0].x), "v"(v[0].y), "v"(v[0].z), "v"(v[0].w), "s"(r)
+      : "scc");
+}
+
+template <>
+__device__ inline void add_shifted<2>(float4 (&acc)[2], const float4 (&v)[2], int r) {
+  asm(
+      "s_cmp_eq_u32 %16, 0\n\t"
+      "s_cbranch_scc1 .Lr0_%=\n\t"
+      "s_cmp_eq_u32 %16, 1\n\t"
+      "s_cbranch_scc1 .Lr1_%=\n\t"
+      "s_cmp_eq_u32 %16, 2\n\t"
+      "s_cbranch_scc1 .Lr2_%=\n\t"
+      "v_add_f32 %0, %11, %0\n\t"
+      "v_add_f32 %4, %15, %4\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %1, %8, %1 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %2, %9, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %10, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %5, %12, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %6, %13, %6 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %7, %14, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr0_%=:\n\t"
+      "v_add_f32 %0, %8, %0\n\t"
+      "v_add_f32 %1, %9, %1\n\t"
+      "v_add_f32 %2, %10, %2\n\t"
+      "v_add_f32 %3, %11, %3\n\t"
+      "v_add_f32 %4, %12, %4\n\t"
+      "v_add_f32 %5, %13, %5\n\t"
+      "v_add_f32 %6, %14, %6\n\t"
+      "v_add_f32 %7, %15, %7\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr1_%=:\n\t"
+      "v_add_f32 %0, %9, %0\n\t"
+      "v_add_f32 %1, %10, %1\n\t"
+      "v_add_f32 %2, %11, %2\n\t"
+      "v_add_f32 %4, %13, %4\n\t"
+      "v_add_f32 %5, %14, %5\n\t"
+      "v_add_f32 %6, %15, %6\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %3, %8, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %7, %12, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "s_branch .Lend_%=\n\t"
+      ".Lr2_%=:\n\t"
+      "v_add_f32 %0, %10, %0\n\t"
+      "v_add_f32 %1, %11, %1\n\t"
+      "v_add_f32 %4, %14, %4\n\t"
+      "v_add_f32 %5, %15, %5\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %2, %8, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %9, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %6, %12, %6 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %7, %13, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      ".Lend_%=:"
+      : "+v"(acc[0].x), "+v"(acc[0].y), "+v"(acc[0].z), "+v"(acc[0].w), "+v"(acc[1].x), "+v"(acc[1].y), "+v"(acc[1].z), "+v"(acc[1].w)
+      : "v"(v[0].x), "v"(v[0].y), "v"(v[0].z), "v"(v[0].w), "v"(v[1].x), "v"(v[1].y), "v"(v[1].z), "v"(v[1].w), "s"(r)
+      : "scc");
+}
+
 // One (DM block, time tile) of one launch item; all threads of the
 // workgroup call it.  lds: the dynamic LDS of the workgroup.
 template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
@@ -199,7 +307,14 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   constexpr int kProducers = 4;
   constexpr int NSW = WS ? kProducers : NW;        // staging waves
   constexpr int NAW = WS ? NW - kProducers : NW;   // accumulating waves
-  constexpr int BD = NAW * G, BT = 256 * Q;
+  // P bit 5: one staged copy per channel.  A window then starts anywhere in
+  // an aligned quad; each lane reads the aligned quads and takes the samples
+  // past its quad from the next lane (DPP), so lane 63 of a 256-sample stripe
+  // yields no outputs and stripes advance by 252 samples.
+  constexpr bool SC = (P & 32) != 0;
+  constexpr int NCP = SC ? 1 : 4;                  // staged copies per channel
+  constexpr int STRIPE = SC ? 252 : 256;           // outputs per stripe
+  constexpr int BD = NAW * G, BT = STRIPE * Q;
   // staging: NSW >= BC: WPR waves share a row and split its quads (each a
   // contiguous range, one quad of overlap); NSW < BC: each wave stages RPW
   // whole rows.  KM quads per lane and row cover rows of up to
@@ -210,7 +325,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   constexpr int KM = RPW > 1 ? kStageQuads / RPW : (QWMAX + 63) / 64;
   static_assert((G == 2 || G % 4 == 0) && (NSW >= BC ? NSW % BC == 0 : BC % NSW == 0) &&
                 (RPW == 1 || RPW * KM == kStageQuads) && BD * BC <= 64 * NSW &&
-                kAccGroup % BC == 0 && (!WS || ((P & 2) != 0 && NAW > 0)), "tiling");
+                kAccGroup % BC == 0 && (!WS || ((P & 2) != 0 && NAW > 0)) && (!SC || (P & 5) == 0),
+                "tiling");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -233,12 +349,12 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // ring position of chunk sample 0
   const int32_t pv = (RING && A.R > 0) ? (int32_t)((p0 + vring) % A.R) : 0;
   const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;   // DM d0's delays
-  // LDS: one stage (or two, double-buffered) of BC rows x 4 copies x RS
+  // LDS: one stage (or two, double-buffered) of BC rows x NCP copies x RS
   // samples followed by the stage's [BC][BD] window offsets
   constexpr bool DB = (P & 2) != 0;
-  const int stage_floats = BC * 4 * RS + BC * BD;
+  const int stage_floats = BC * NCP * RS + BC * BD;
   auto stage_rows = [&](int b) { return lds + b * stage_floats; };
-  auto stage_off = [&](int b) { return reinterpret_cast<int*>(lds + b * stage_floats + BC * 4 * RS); };
+  auto stage_off = [&](int b) { return reinterpret_cast<int*>(lds + b * stage_floats + BC * NCP * RS); };
 
   auto row_of = [&](int rr) { return NSW >= BC ? wave / WPR : wave + NSW * rr; };
   // this wave's quads of its row(s): [m0, mend); the last quad of a range
@@ -261,31 +377,45 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   int offreg[NSET] = {};
 
   // Cleaning metadata of row c (vector loads: they count on vmcnt only, so
-  // nothing scalar is pending while LDS reads are in flight).
+  // nothing scalar is pending while LDS reads are in flight).  Both words
+  // are loaded from clamped indices on every path, with nothing computed
+  // from them until the block is written: a block's loads never depend on
+  // the data and nothing waits for them early, so they stay in flight
+  // behind the next block's.  A window with no chunk sample never reads the
+  // words; one whose chunks all fit the first word never reads the second.
   auto load_meta = [&](RowMeta& m, int c, int64_t a) {
     m.a = a;
     if (CLEAN) {
-      int64_t tlo = a - vring, thi = a - vring + RS + 4;
+      int64_t tlo = a - vring;
       tlo = tlo < 0 ? 0 : (tlo > A.L ? A.L : tlo);
-      thi = thi < 0 ? 0 : (thi > A.L ? A.L : thi);
-      if (thi <= tlo) { m.j0 = 0; m.m_lo = m.m_hi = 0; return; }
-      const int jlo = (int)chunk_of(A.clean, tlo);
-      const int w0 = jlo >> 5;
+      const int w0 = (int)chunk_of(A.clean, tlo) >> 5;
+      const int jw = (int)A.clean.JW;
       m.j0 = w0 * 32;
       const int vz = lane * A.zero;     // 0, but lane-dependent: vector loads
       const uint32_t* cb = A.clean.cbits + (int64_t)c * A.clean.JW + vz;
-      m.m_lo = cb[w0];
-      m.m_hi = (w0 + 1 < A.clean.JW) ? cb[w0 + 1] : 0u;
+      m.m_lo = cb[max(min(w0, jw - 1), 0)];
+      m.m_hi = cb[max(min(w0 + 1, jw - 1), 0)];
     }
   };
 
+  // Issues the loads of channel block cb0.  Rows past the last channel (and
+  // blocks past the end) load a valid row instead, whose values are never
+  // written: every call issues the same loads, see load_meta.
   auto issue_block = [&](int cb0, auto set_c) {
     constexpr int S = decltype(set_c)::value;
+    // the window bases of the rows of the block after this one go first:
+    // the next call waits for them, and so for nothing issued after them
+    int base_now[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
-      const int c = cb0 + row_of(rr);
-      if (c < C) {
-        const int base = __builtin_amdgcn_readfirstlane(basen[rr]);
+      base_now[rr] = __builtin_amdgcn_readfirstlane(basen[rr]);
+      basen[rr] = dl[min(cb0 + BC + row_of(rr), C - 1) + lane * A.zero];
+    }
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int c = min(cb0 + row_of(rr), C - 1);
+      {
+        const int base = base_now[rr];
         const int64_t a = t0 + (base & ~3);
         const int32_t aw = (int32_t)(a - vring);     // chunk index of the window start
         rowt[S][rr] = aw;
@@ -299,8 +429,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           issue<TIN, CLEAN, RING>(st[S][rr][k], A, xrow, ringrow, aw + 4 * m, m < mend, pv);
         }
       }
-      const int cn = cb0 + BC + row_of(rr);
-      if (cn < C) basen[rr] = dl[cn + lane * A.zero];
     }
     {
       // unconditional load from a clamped index (no load inside a divergent
@@ -324,7 +452,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     for (int rr = 0; rr < RPW; ++rr) {
       const int cb = row_of(rr);
       const int c = cb0 + cb;
-      float* row = rows + cb * 4 * RS;
+      float* row = rows + cb * NCP * RS;
       if (c >= C) {
         // rows past the last channel read as zeros (offset 0 of copy 0), so
         // the accumulation of a block needs no per-channel bound test
@@ -356,8 +484,18 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           }
         } else {
 #pragma unroll
-          for (int k = 0; k < KM; ++k) lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit);
+          for (int k = 0; k < KM; ++k) {
+            const int m = m0 + lane + 64 * k;
+            lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit, rowt[S][rr] + 4 * m, m < mend);
+          }
         }
+        if constexpr (SC) {
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            const int m = m0 + lane + 64 * k;
+            if (m < mend) *reinterpret_cast<float4*>(row + 4 * m) = lo[k];
+          }
+        } else {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           float4 hi;
@@ -384,24 +522,29 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
             }
           }
         }
+        }
       }
     }
     if (tid < BD * BC) lds_off[tid] = (cb0 + tid / BD < C) ? offreg[S] : 0;   // [cb][dd], dd fastest
   };
 
+  // Running sums; zeroed where the accumulating loop starts, so that they
+  // are not live while producers stage.
   float4 acc[G][Q], tot[G][Q];
+  auto zero_sums = [&] {
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      acc[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      tot[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+      for (int q = 0; q < Q; ++q) {
+        acc[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        tot[g][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+  };
 
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     const int c = row_of(rr);
-    basen[rr] = c < C ? dl[c] : 0;
+    basen[rr] = dl[min(c, C - 1)];
   }
   // Single buffer: per block, issue the loads of block k+1, accumulate block
   // k, barrier, write block k+1, barrier.  Double buffer: block k+1 is
@@ -415,7 +558,39 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     // Straight-line over the BC channels (rows past C are zeros).
     const char* base = reinterpret_cast<const char*>(stage_rows(cur)) + 16 * lane;
     const int* lds_off = stage_off(cur);
-    if constexpr ((P & 4) != 0) {
+    if constexpr (SC) {
+      // The block's window offsets first (uniform: SGPRs), then per DM the
+      // adds of channel cb, routed by the window's residue r (element e of a
+      // lane's outputs is element e + r of its aligned quad, or e + r - 4 of
+      // the next lane's), each followed at once by the reads of channel
+      // cb+1 into the same registers.  The values and the order of the adds
+      // are those of the four-copy layout.
+      int offs[BC][G];
+#pragma unroll
+      for (int cb = 0; cb < BC; ++cb) {
+        int o[G];
+        load_offsets(lds_off + cb * BD + aw * G, o);
+#pragma unroll
+        for (int g = 0; g < G; ++g) offs[cb][g] = __builtin_amdgcn_readfirstlane(o[g]);
+      }
+      float4 v[G][Q];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[g][q] = reinterpret_cast<const float4*>(base + (offs[0][g] & ~3))[63 * q];
+#pragma unroll
+      for (int cb = 0; cb < BC; ++cb) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          add_shifted<Q>(acc[g], v[g], offs[cb][g] & 3);
+          if (cb + 1 < BC) {
+            const char* rowb = base + (cb + 1) * 4 * RS + (offs[cb + 1][g] & ~3);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[g][q] = reinterpret_cast<const float4*>(rowb)[63 * q];
+          }
+        }
+      }
+    } else if constexpr ((P & 4) != 0) {
       // pipelined: two register sets; the reads of channel cb+1 and the
       // offsets of channel cb+2 are issued before the adds of channel cb
       // (for tilings whose occupancy does not drop with the extra registers)
@@ -528,44 +703,46 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   if (stager) {
     issue_block(0, Set0{});
     write_block(0, 0, Set0{});
-    if (DB && BC < C) issue_block(BC, Set0{});
-    if (PF2 && 2 * BC < C) issue_block(2 * BC, SetL{});
+    if (DB) issue_block(BC, Set0{});
+    if (PF2) issue_block(2 * BC, SetL{});
   }
   __syncthreads();
   if constexpr (WS) {
     if (stager) {
       if constexpr (PF2) {
         // block k+1 sits in set k & 1: two steps per iteration keep the set
-        // indices compile-time; each step writes block k+1, issues block
-        // k+3 into the set it freed, and ends with the block's barrier
+        // indices compile-time; each step writes block k+1 and issues block
+        // k+3 into the set it freed.  The issues are unconditional (past the
+        // end they load rows that are never written) so that the wait for a
+        // set only ever covers that set; the second step's barrier exists
+        // only when its block does, so producers and consumers execute the
+        // same number of barriers.
         int cur = 0;
-        auto step = [&](int cb0, auto set_c) {
-          const int next = cb0 + BC;
-          if (next < C) {
-            write_block(next, cur ^ 1, set_c);
-            if (next + 2 * BC < C) issue_block(next + 2 * BC, set_c);
-          }
+        for (int cb0 = 0; cb0 < C; cb0 += 2 * BC) {
+          if (cb0 + BC < C) write_block(cb0 + BC, cur ^ 1, Set0{});
+          issue_block(cb0 + 3 * BC, Set0{});
           __syncthreads();
           cur ^= 1;
-        };
-        for (int cb0 = 0; cb0 < C; cb0 += 2 * BC) {
-          step(cb0, Set0{});
-          if (cb0 + BC < C) step(cb0 + BC, SetL{});
+          if (cb0 + 2 * BC < C) write_block(cb0 + 2 * BC, cur ^ 1, SetL{});
+          issue_block(cb0 + 4 * BC, SetL{});
+          if (cb0 + BC < C) {
+            __syncthreads();
+            cur ^= 1;
+          }
         }
       } else {
         int cur = 0;
         for (int cb0 = 0; cb0 < C; cb0 += BC) {
           const int next = cb0 + BC;
-          if (next < C) {
-            write_block(next, cur ^ 1, Set0{});
-            if (next + BC < C) issue_block(next + BC, Set0{});
-          }
+          if (next < C) write_block(next, cur ^ 1, Set0{});
+          issue_block(next + BC, Set0{});          // past the end: unused
           __syncthreads();
           cur ^= 1;
         }
       }
       return;                   // producers hold no outputs
     }
+    zero_sums();
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
       accumulate(cb0, cur);
@@ -573,14 +750,13 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       cur ^= 1;
     }
   } else {
+    zero_sums();
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
       const int next = cb0 + BC;
       if constexpr (DB) {
-        if (next < C) {
-          write_block(next, cur ^ 1, Set0{});
-          if (next + BC < C) issue_block(next + BC, Set0{});
-        }
+        if (next < C) write_block(next, cur ^ 1, Set0{});
+        issue_block(next + BC, Set0{});            // past the end: unused
       } else {
         if (next < C) issue_block(next, Set0{});
       }
@@ -611,7 +787,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     float* orow = A.out + (int64_t)d * A.ld_out;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int64_t j = t0 + 4 * lane + 256 * q - A.phase;
+      if (SC && lane == 63) continue;          // feeds lane 62 only
+      const int64_t j = t0 + 4 * lane + STRIPE * q - A.phase;
       if (A.phase == 0 && j + 3 < A.nout) {
         *reinterpret_cast<float4*>(orow + j) = tot[g][q];
       } else {
@@ -668,18 +845,20 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 // Advances a beam's device-side sample count after a chunk.
 __global__ void beam_advance_kernel(int64_t* seen, int64_t L) { *seen += L; }
 
-// Per-(DM, channel) LDS byte offset of the DM's window inside the channel's
-// 4-copy region: with p = s[d][c] - (s[d0][c] & ~3), the window starts at
-// position p & ~3 of copy p & 3.
+// Per-(DM, channel) window offset inside the channel's staged region, with
+// p = s[d][c] - (s[d0][c] & ~3).  Four copies: the window starts at position
+// p & ~3 of copy p & 3 (LDS byte offset).  One copy: byte offset of the
+// aligned quad holding the window start, p & ~3, with the residue p & 3 in
+// the two low bits (the offset itself is a multiple of 16).
 __global__ void relb_kernel(const int32_t* __restrict__ delays, int32_t C, int32_t ndms, int32_t BD,
-                            int32_t RS, int32_t ldr, int32_t* __restrict__ relb) {
+                            int32_t RS, int32_t copies, int32_t ldr, int32_t* __restrict__ relb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)ldr * ndms) return;
   const int32_t d = (int32_t)(i / ldr), c = (int32_t)(i % ldr);
   if (c >= C) { relb[i] = 0; return; }
   const int32_t d0 = (d / BD) * BD;
   const int32_t p = delays[(int64_t)d * C + c] - (delays[(int64_t)d0 * C + c] & ~3);
-  relb[i] = ((p & 3) * RS + (p & ~3)) * 4;
+  relb[i] = copies == 1 ? (p & ~3) * 4 + (p & 3) : ((p & 3) * RS + (p & ~3)) * 4;
 }
 
 // Ring update: write the chunk's last min(L, R) cleaned samples at ring
@@ -704,13 +883,23 @@ __global__ __launch_bounds__(256) void ring_update_kernel(const TIN* __restrict_
   ring[(int64_t)c * R + (seen + t) % R] = v;
 }
 
+// The P a kernel variant is compiled with: the second prefetch set (P bit 4)
+// does not fit the registers of the persistent kernel or of a ring kernel
+// fed uint8 / FP16 (which also holds the ring's FP32 values), so those keep
+// one block in flight.  The LDS layout and every addition are the same.
+template <typename TIN>
+constexpr int kernel_p(int P, bool ring, bool batch) {
+  return ((P & 16) != 0 && (batch || (ring && !std::is_same<TIN, float>::value))) ? (P & ~16) : P;
+}
+
 template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
 hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit32, size_t lds,
                       hipStream_t s) {
   // the LDS limit was raised when the plan was created (dedisp_prepare), so
   // a launch makes no attribute call and is safe inside stream capture
   const unsigned grid = (unsigned)a.n_dblocks * (unsigned)a.n_ttiles;
-  hipLaunchKernelGGL((dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC, P>), dim3(grid), dim3(64 * NW), lds, s,
+  constexpr int KP = kernel_p<TIN>(P, RING, false);
+  hipLaunchKernelGGL((dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC, KP>), dim3(grid), dim3(64 * NW), lds, s,
                      a, relb, fit32);
   return hipGetLastError();
 }
@@ -719,12 +908,15 @@ hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit
 // lane, channels per LDS stage, P: bit 0 rolling accumulation, bit 1 double-
 // buffered LDS stages, bit 2 pipelined accumulation with two register sets,
 // bit 3 warp specialisation: four producer waves, the rest consumers, bit 4
-// with bit 3: producers keep two blocks of loads in flight).
-// The plan takes the first that fits its LDS and staging limits: the last
-// four, with 16 and 8 DMs per block, serve DM grids whose delay spread per
-// DM step is large (coarse steps, slow sampling).
-#define MBTP_TILINGS(X) X(12, 4, 2, 4, 10) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(8, 4, 2, 4, 2) \
-  X(12, 2, 2, 4, 10) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0)
+// with bit 3: producers keep two blocks of loads in flight, bit 5: one
+// staged copy per channel).
+// The plan takes the first that fits its LDS and staging limits.  The four
+// with 16 and 8 DMs per block serve DM grids whose delay spread per DM step
+// is large (coarse steps, slow sampling).  The last stages one copy per
+// channel (a quarter of the LDS writes, residues routed in the adds): the
+// autotuner may pick it where staging dominates.
+#define MBTP_TILINGS(X) X(12, 4, 2, 4, 26) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(8, 4, 2, 4, 2) \
+  X(12, 2, 2, 4, 26) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0) X(12, 4, 2, 4, 42)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,
@@ -747,10 +939,10 @@ int n_tilings() { return (int)(sizeof(kTilings) / sizeof(kTilings[0])); }
 Tiling tiling_at(int i) { return kTilings[i]; }
 
 hipError_t launch_relb(const int32_t* delays, int32_t C, int32_t ndms, int32_t BD, int32_t RS,
-                       int32_t ldr, int32_t* relb, hipStream_t s) {
+                       int32_t copies, int32_t ldr, int32_t* relb, hipStream_t s) {
   const int64_t n = (int64_t)ldr * ndms;
   hipLaunchKernelGGL(relb_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, delays, C,
-                     ndms, BD, RS, ldr, relb);
+                     ndms, BD, RS, copies, ldr, relb);
   return hipGetLastError();
 }
 
@@ -799,7 +991,8 @@ template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC, int P>
 hipError_t launch_batch_one(BatchArgs& b, size_t lds, int grid_cap, hipStream_t s) {
   const int grid = b.total < grid_cap ? b.total : grid_cap;
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, b.counter);
-  hipLaunchKernelGGL((dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC, P>), dim3(grid), dim3(64 * NW), lds, s, b);
+  hipLaunchKernelGGL((dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC, kernel_p<TIN>(P, true, true)>), dim3(grid),
+                     dim3(64 * NW), lds, s, b);
   return hipGetLastError();
 }
 
@@ -808,13 +1001,15 @@ hipError_t launch_batch_one(BatchArgs& b, size_t lds, int grid_cap, hipStream_t 
 // bytes, without and with cleaning.
 template <typename TIN, int NW, int G, int Q, int BC, int P>
 hipError_t prepare_one(size_t lds, int occ[2]) {
+  constexpr int P0 = kernel_p<TIN>(P, false, false), PR = kernel_p<TIN>(P, true, false),
+                PB = kernel_p<TIN>(P, true, true);
   const void* ks[6] = {
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, true, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, true, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, true, NW, G, Q, BC, P>)};
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, false, NW, G, Q, BC, P0>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, true, NW, G, Q, BC, PR>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, false, NW, G, Q, BC, P0>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, true, NW, G, Q, BC, PR>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, false, NW, G, Q, BC, PB>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, true, NW, G, Q, BC, PB>)};
   hipError_t e;
   for (const void* k : ks) {
     // dynamic + static LDS of a workgroup must fit the CU's 160 KiB

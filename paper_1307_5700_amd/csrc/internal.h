@@ -148,7 +148,11 @@ struct Tiling {
   int P;              // bit 0: rolling accumulation loop; bit 1: two LDS stages
   int staging_waves() const { return (P & 8) ? 4 : NW; }           // P bit 3: 4 producers
   int BD() const { return ((P & 8) ? NW - 4 : NW) * G; }            // consumers x G
-  int BT() const { return 256 * Q; }
+  // P bit 5: one staged copy per channel (lane 63 of every 256-sample stripe
+  // only feeds its neighbour, so a stripe yields 252 outputs); else four
+  // shifted copies
+  int copies() const { return (P & 32) ? 1 : 4; }
+  int BT() const { return ((P & 32) ? 252 : 256) * Q; }
   int threads() const { return 64 * NW; }
 };
 
@@ -161,7 +165,7 @@ Tiling tiling_at(int i);
 
 // Per-(DM, channel) LDS byte offsets of a tiling (see dedisp.hip).
 hipError_t launch_relb(const int32_t* delays, int32_t C, int32_t ndms, int32_t BD, int32_t RS,
-                       int32_t ldr, int32_t* relb, hipStream_t s);
+                       int32_t copies, int32_t ldr, int32_t* relb, hipStream_t s);
 
 hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, const DedispArgs& a,
                          const int32_t* relb, const float* fit32, size_t lds_bytes,

@@ -133,8 +133,8 @@ constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, less
 void tiling_geometry(const mb_plan& p, const Tiling& t, int& rs, size_t& lds) {
   const int sp = span_max(p, t.BD());
   rs = (t.BT() + sp + 7 + 3) & ~3;
-  // four shifted copies per channel, then the block's [BC][BD] offsets
-  lds = ((size_t)t.BC * 4 * rs * sizeof(float) + (size_t)t.BC * t.BD() * sizeof(int32_t)) *
+  // the staged copies of each channel, then the block's [BC][BD] offsets
+  lds = ((size_t)t.BC * t.copies() * rs * sizeof(float) + (size_t)t.BC * t.BD() * sizeof(int32_t)) *
         ((t.P & 2) ? 2 : 1);   // P bit 1: two stages (double buffer)
 }
 
@@ -278,7 +278,8 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
   e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e == hipSuccess) e = dedisp_prepare(d.in_dtype, p->tiling, p->lds, p->batch_occ);
   if (e == hipSuccess) e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->relb_ld, p->d_relb, nullptr);
+  if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->tiling.copies(),
+                                        p->relb_ld, p->d_relb, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     (void)hipFree(p->d_delays);

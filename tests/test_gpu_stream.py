@@ -112,3 +112,34 @@ def test_stream_chunks_must_be_multiples_of_4():
         plan.execute(x[:, :1001], beam=bm)
     assert e.value.status == A.L.MB_EINVAL
     assert bm.position() == 0
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_stream_tiling_does_not_change_a_bit(dtype):
+    """Every compiled tiling streams the same chunks (with RFI) to the same
+    bits: the ring kernels, the one-copy staging and the launch-time choice
+    of prefetch depth change no addition."""
+    A = api()
+    beam, s = _stream_beam(dtype=dtype, nd=96, T=3 * 8192, seed=67)
+    x = synth.render(beam, s)
+    lens = [8192, 8192, 8192]
+    ref, used = None, set()
+    for hint in range(1, A.num_tilings() + 1):
+        try:
+            plan = A.Plan.from_beam(beam, tile_hint=hint)
+        except A.L.MbError:
+            continue
+        used.add(plan.tiling["index"])
+        bm = A.Beam(plan)
+        outs, a = [], 0
+        for L_ in lens:
+            xd = to_dev(x[:, a:a + L_])
+            a += L_
+            out, _, nout, s0 = plan.execute(xd, rfi_state=plan.rfi_threshold(xd), beam=bm)
+            outs.append((s0, out[:, :nout].cpu().numpy()))
+        if ref is None:
+            ref = outs
+        else:
+            for k, ((s0, D), (r0, R)) in enumerate(zip(outs, ref)):
+                assert s0 == r0 and np.array_equal(D, R), (hint, k)
+    assert len(used) >= 4
