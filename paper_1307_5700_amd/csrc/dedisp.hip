@@ -700,15 +700,19 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   const bool stager = !WS || wave < kProducers;
   using Set0 = std::integral_constant<int, 0>;
   using SetL = std::integral_constant<int, NSET - 1>;   // second set (or set 0)
-  if (stager) {
+  auto prologue = [&] {
     issue_block(0, Set0{});
     write_block(0, 0, Set0{});
     if (DB) issue_block(BC, Set0{});
     if (PF2) issue_block(2 * BC, SetL{});
-  }
-  __syncthreads();
+  };
   if constexpr (WS) {
+    // Each role's whole life sits in its own branch (the first barrier
+    // included), so no staging register is live in the accumulating loop
+    // and the kernel needs the larger role's registers, not their sum.
     if (stager) {
+      prologue();
+      __syncthreads();
       if constexpr (PF2) {
         // block k+1 sits in set k & 1: two steps per iteration keep the set
         // indices compile-time; each step writes block k+1 and issues block
@@ -742,6 +746,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       }
       return;                   // producers hold no outputs
     }
+    __syncthreads();
     zero_sums();
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
@@ -750,6 +755,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
       cur ^= 1;
     }
   } else {
+    prologue();
+    __syncthreads();
     zero_sums();
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
@@ -884,12 +891,13 @@ __global__ __launch_bounds__(256) void ring_update_kernel(const TIN* __restrict_
 }
 
 // The P a kernel variant is compiled with: the second prefetch set (P bit 4)
-// does not fit the registers of the persistent kernel or of a ring kernel
-// fed uint8 / FP16 (which also holds the ring's FP32 values), so those keep
-// one block in flight.  The LDS layout and every addition are the same.
+// does not fit the registers of the persistent kernel (its tile loop holds
+// more state), which keeps one block in flight.  The LDS layout and every
+// addition are the same.
 template <typename TIN>
 constexpr int kernel_p(int P, bool ring, bool batch) {
-  return ((P & 16) != 0 && (batch || (ring && !std::is_same<TIN, float>::value))) ? (P & ~16) : P;
+  (void)ring;
+  return ((P & 16) != 0 && batch) ? (P & ~16) : P;
 }
 
 template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
@@ -910,13 +918,15 @@ hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit
 // bit 3 warp specialisation: four producer waves, the rest consumers, bit 4
 // with bit 3: producers keep two blocks of loads in flight, bit 5: one
 // staged copy per channel).
-// The plan takes the first that fits its LDS and staging limits.  The four
-// with 16 and 8 DMs per block serve DM grids whose delay spread per DM step
-// is large (coarse steps, slow sampling).  The last stages one copy per
-// channel (a quarter of the LDS writes, residues routed in the adds): the
-// autotuner may pick it where staging dominates.
-#define MBTP_TILINGS(X) X(12, 4, 2, 4, 26) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) X(8, 4, 2, 4, 2) \
-  X(12, 2, 2, 4, 26) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0) X(12, 4, 2, 4, 42)
+// The plan takes the first that fits its LDS and staging limits: 48 DMs per
+// block first (twelve consumer waves share every staged block), then 32.
+// The four with 16 and 8 DMs per block serve DM grids whose delay spread per
+// DM step is large (coarse steps, slow sampling).  The last stages one copy
+// per channel (a quarter of the LDS writes, residues routed in the adds):
+// the autotuner may pick it where staging dominates.
+#define MBTP_TILINGS(X) X(16, 4, 2, 4, 26) X(12, 4, 2, 4, 26) X(8, 4, 2, 8, 0) X(16, 2, 2, 4, 3) \
+  X(8, 4, 2, 4, 2) X(12, 2, 2, 4, 26) X(4, 4, 2, 4, 0) X(4, 2, 2, 4, 0) X(4, 2, 1, 4, 0)         \
+  X(12, 4, 2, 4, 42)
 
 template <typename TIN, bool CLEAN, bool RING>
 hipError_t launch_tiled(const Tiling& t, const DedispArgs& a, const int32_t* relb,
