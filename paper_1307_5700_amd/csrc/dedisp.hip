@@ -185,6 +185,16 @@ __device__ inline void load_offsets(const int* src, int (&o)[G]) {
   }
 }
 
+// x of the next lane; lane 63 (no next lane) returns old.
+__device__ inline float next_quad(float x, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+
+// x of the next lane, lane 63 taking lane 0's (wave rotate).
+__device__ inline float wave_rotate(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xf, 0xf, false));
+}
+
 // acc[q] += the 4 window samples that start r (uniform, 0..3) samples into
 // the lane's aligned quad v[q]; the samples past the quad are the next
 // lane's, taken by a DPP wave shift fused into the add (lane 63 adds 0).
@@ -294,9 +304,9 @@ __device__ inline void add_shifted<2>(float4 (&acc)[2], const float4 (&v)[2], in
 
 // One (DM block, time tile) of one launch item; all threads of the
 // workgroup call it.  lds: the dynamic LDS of the workgroup.
-template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
-__device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* __restrict__ relb,
-                                            const float* __restrict__ fit32, float* lds,
+template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P, bool SKIP_IDLE>
+__device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* relb,
+                                            const float* fit32, float* lds,
                                             int dblock, int ttile) {
   // P bit 3: warp specialisation.  The first kProducers waves only stage
   // (producers), the others only accumulate (consumers), each role in its
@@ -460,7 +470,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           *reinterpret_cast<float4*>(row + 4 * m) = make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
         const float fit = CLEAN ? fitn[S][rr] : 0.0f;
-        float4 lo[KM];
         // Fast path (uniform per row): the wave's quads all lie inside the
         // chunk and none of their chunks or spectra is flagged, so a quad
         // needs only widening and the bandpass subtraction.
@@ -473,7 +482,45 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
           const uint32_t mbits = __builtin_amdgcn_readfirstlane(rm[S][rr].m_lo | rm[S][rr].m_hi);
           fast = fast && mbits == 0 && __builtin_amdgcn_ballot_w64(gor != 0) == 0;
         }
+        // Writes the cleaned quads lo[] (each branch below has its own copy,
+        // so the two cleaning paths need no register moves to merge).
+        auto write_quads = [&](const float4 (&lo)[KM]) {
+          if constexpr (SC) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+              const int m = m0 + lane + 64 * k;
+              if (m < mend) *reinterpret_cast<float4*>(row + 4 * m) = lo[k];
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+              // hi = the first three samples of the next quad: the next
+              // lane's (wave shift); lane 63 keeps the `old` operand, lane
+              // 0's quad of k+1 brought over by a wave rotate.  The last
+              // k's lane 63 feeds no window.
+              float4 hi;
+              const float4 nx = lo[(k + 1) % KM];
+              const bool more = k + 1 < KM;
+              hi.x = next_quad(lo[k].x, more ? wave_rotate(nx.x) : 0.0f);
+              hi.y = next_quad(lo[k].y, more ? wave_rotate(nx.y) : 0.0f);
+              hi.z = next_quad(lo[k].z, more ? wave_rotate(nx.z) : 0.0f);
+              const int m = m0 + lane + 64 * k;
+              if (m < mend) {
+                const float4 l = lo[k];
+                // copy r holds the window shifted by r samples
+                float* p = row + 4 * m;
+                *reinterpret_cast<float4*>(p) = l;
+                if (WPR == 1 || m + 1 < mend || wr == WPR - 1) {
+                  *reinterpret_cast<float4*>(p + RS) = make_float4(l.y, l.z, l.w, hi.x);
+                  *reinterpret_cast<float4*>(p + 2 * RS) = make_float4(l.z, l.w, hi.x, hi.y);
+                  *reinterpret_cast<float4*>(p + 3 * RS) = make_float4(l.w, hi.x, hi.y, hi.z);
+                }
+              }
+            }
+          }
+        };
         if (fast) {
+          float4 lo[KM];
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
             float4 f;
@@ -482,46 +529,15 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
             if (CLEAN) { f.x -= fit; f.y -= fit; f.z -= fit; f.w -= fit; }
             lo[k] = f;
           }
+          write_quads(lo);
         } else {
+          float4 lo[KM];
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
             const int m = m0 + lane + 64 * k;
             lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit, rowt[S][rr] + 4 * m, m < mend);
           }
-        }
-        if constexpr (SC) {
-#pragma unroll
-          for (int k = 0; k < KM; ++k) {
-            const int m = m0 + lane + 64 * k;
-            if (m < mend) *reinterpret_cast<float4*>(row + 4 * m) = lo[k];
-          }
-        } else {
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          float4 hi;
-          hi.x = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(lo[k].x), 0x130, 0xf, 0xf, false));
-          hi.y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(lo[k].y), 0x130, 0xf, 0xf, false));
-          hi.z = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(lo[k].z), 0x130, 0xf, 0xf, false));
-          if (k + 1 < KM) {
-            const float4 nx = lo[(k + 1) % KM];
-            const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nx.x), 0));
-            const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nx.y), 0));
-            const float az = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nx.z), 0));
-            if (lane == 63) { hi.x = ax; hi.y = ay; hi.z = az; }
-          }
-          const int m = m0 + lane + 64 * k;
-          if (m < mend) {
-            const float4 l = lo[k];
-            // copy r holds the window shifted by r samples
-            float* p = row + 4 * m;
-            *reinterpret_cast<float4*>(p) = l;
-            if (WPR == 1 || m + 1 < mend || wr == WPR - 1) {
-              *reinterpret_cast<float4*>(p + RS) = make_float4(l.y, l.z, l.w, hi.x);
-              *reinterpret_cast<float4*>(p + 2 * RS) = make_float4(l.z, l.w, hi.x, hi.y);
-              *reinterpret_cast<float4*>(p + 3 * RS) = make_float4(l.w, hi.x, hi.y, hi.z);
-            }
-          }
-        }
+          write_quads(lo);
         }
       }
     }
@@ -705,6 +721,11 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     write_block(0, 0, Set0{});
     if (DB) issue_block(BC, Set0{});
     if (PF2) issue_block(2 * BC, SetL{});
+    // keeps the compiler from sinking any of these loads below the first
+    // barrier into the loop's preheader: the wait counts at the loop head
+    // hold for every path into it, so one late load there would make the
+    // first step of every iteration wait for all loads
+    asm volatile("" ::: "memory");
   };
   if constexpr (WS) {
     // Each role's whole life sits in its own branch (the first barrier
@@ -748,9 +769,13 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     }
     __syncthreads();
     zero_sums();
+    // a consumer whose DMs all lie past the grid's last (the last DM block
+    // of a grid that BD does not divide) reads nothing, but keeps the
+    // barriers (not in the persistent kernel, whose registers are full)
+    const bool idle = SKIP_IDLE && d0 + aw * G > dlast;
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
-      accumulate(cb0, cur);
+      if (!idle) accumulate(cb0, cur);
       __syncthreads();
       cur ^= 1;
     }
@@ -809,8 +834,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
 }
 
 template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
-__global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int32_t* __restrict__ relb,
-                                                         const float* __restrict__ fit32) {
+__global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int32_t* relb,
+                                                         const float* fit32) {
   extern __shared__ float4 lds4[];
   // Workgroup id -> tile.  Consecutive workgroups go to different XCDs; give
   // each XCD a contiguous range of tiles, DM block fastest, so the blocks
@@ -820,7 +845,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
   const int xcd = bid & 7, slot = bid >> 3;
   const int q8 = ntile >> 3, rem = ntile & 7;
   const int tile = xcd * q8 + min(xcd, rem) + slot;
-  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P>(A, relb, fit32, reinterpret_cast<float*>(lds4),
+  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P, true>(A, relb, fit32, reinterpret_cast<float*>(lds4),
                                               tile % A.n_dblocks, tile / A.n_dblocks);
 }
 
@@ -842,7 +867,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_batch_kernel(BatchArgs B) {
     while (i + 1 < B.nitems && t >= B.item[i + 1].tile0) ++i;
     const BatchItem& it = B.item[i];
     const int local = t - it.tile0;
-    dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC, P>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
+    dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC, P, false>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
                                                 local % it.a.n_dblocks, local / it.a.n_dblocks);
   }
 }
