@@ -839,14 +839,38 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
   extern __shared__ float4 lds4[];
   // Workgroup id -> tile.  Consecutive workgroups go to different XCDs; give
   // each XCD a contiguous range of tiles, DM block fastest, so the blocks
-  // that share a time tile run on the same L2 at about the same time.
-  const int ntile = A.n_dblocks * A.n_ttiles;
+  // that share a time tile run on the same L2 at about the same time.  When
+  // the last DM block is partial (its idle consumers make its tiles
+  // cheaper), each XCD takes its share of the full blocks' tiles first and
+  // its share of the partial block's last, so the cheap tiles fill the
+  // final, partly occupied round.
+  constexpr int BD = ((P & 8) ? NW - 4 : NW) * G;
+  const int nd = A.n_dblocks, nt = A.n_ttiles;
+  const int ntile = nd * nt;
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
   const int q8 = ntile >> 3, rem = ntile & 7;
-  const int tile = xcd * q8 + min(xcd, rem) + slot;
+  int dblock, ttile;
+  if (A.ndms % BD != 0 && nd > 1 && nt >= 8) {
+    const int nfull = (nd - 1) * nt;
+    const int f8 = nfull >> 3, frem = nfull & 7;
+    const int nf = f8 + (xcd < frem ? 1 : 0);            // full tiles of this XCD
+    const int fb = xcd * f8 + min(xcd, frem);            // first of them
+    if (slot < nf) {
+      dblock = (fb + slot) % (nd - 1);
+      ttile = (fb + slot) / (nd - 1);
+    } else {
+      dblock = nd - 1;
+      ttile = xcd * q8 + min(xcd, rem) - fb + (slot - nf);
+    }
+  } else {
+    const int tile = xcd * q8 + min(xcd, rem) + slot;
+    dblock = tile % nd;
+    ttile = tile / nd;
+  }
+  if (dblock >= nd || ttile >= nt) return;               // uniform: never taken
   dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P, true>(A, relb, fit32, reinterpret_cast<float*>(lds4),
-                                              tile % A.n_dblocks, tile / A.n_dblocks);
+                                                       dblock, ttile);
 }
 
 // Persistent launch over the tiles of several items (beams, chunks, plans of
