@@ -314,7 +314,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // overlaps the accumulation of block k and neither role holds the other's
   // registers.  Otherwise every wave stages and accumulates.
   constexpr bool WS = (P & 8) != 0;
-  constexpr int kProducers = 4;
+  constexpr int kProducers = (P & 64) ? 8 : 4;      // P bit 6: eight producers
   constexpr int NSW = WS ? kProducers : NW;        // staging waves
   constexpr int NAW = WS ? NW - kProducers : NW;   // accumulating waves
   // P bit 5: one staged copy per channel.  A window then starts anywhere in
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
   // cheaper), each XCD takes its share of the full blocks' tiles first and
   // its share of the partial block's last, so the cheap tiles fill the
   // final, partly occupied round.
-  constexpr int BD = ((P & 8) ? NW - 4 : NW) * G;
+  constexpr int BD = ((P & 8) ? NW - ((P & 64) ? 8 : 4) : NW) * G;
   const int nd = A.n_dblocks, nt = A.n_ttiles;
   const int ntile = nd * nt;
   const int bid = blockIdx.x;

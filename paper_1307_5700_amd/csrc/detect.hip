@@ -183,29 +183,34 @@ __global__ __launch_bounds__(1024) void detect_count_kernel(const float* __restr
   }
 }
 
-// Exclusive scan of the per-(row, segment) counts (one 1024-thread workgroup).
+// Exclusive scan of the per-(row, segment) counts (one 1024-thread
+// workgroup, one pass): each thread sums a contiguous run of counts, the runs'
+// sums are scanned across the wave (shuffles) and across the 16 waves (LDS,
+// one barrier), and each thread writes its run's offsets.
 __global__ __launch_bounds__(1024) void detect_scan_kernel(const int64_t* __restrict__ counts,
                                                            int64_t n, int64_t* __restrict__ offsets,
                                                            int64_t* __restrict__ total) {
-  __shared__ int64_t sh[1024];
-  int64_t carry = 0;
-  for (int64_t base = 0; base < n; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = (i < n) ? counts[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (i < n) offsets[i] = carry + sh[threadIdx.x] - v;
-    const int64_t blk = sh[1023];
-    __syncthreads();
-    carry += blk;
+  __shared__ int64_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = min((int64_t)tid * per, n), e = min(b + per, n);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += counts[i];
+  int64_t inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t o = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += o;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int64_t run = inc - s;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+  if (tid == 1023) *total = run + s;
+  for (int64_t i = b; i < e; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
 }
 
 // Exclusive prefix sum over the 64 lanes of a wave.

@@ -146,8 +146,9 @@ struct Tiling {
   int NW, G, Q, BC;   // waves per workgroup, DMs per wave, float4 groups per lane,
                       // channels per LDS stage
   int P;              // bit 0: rolling accumulation loop; bit 1: two LDS stages
-  int staging_waves() const { return (P & 8) ? 4 : NW; }           // P bit 3: 4 producers
-  int BD() const { return ((P & 8) ? NW - 4 : NW) * G; }            // consumers x G
+  // P bit 3: warp specialisation with 4 producer waves (8 with P bit 6)
+  int staging_waves() const { return (P & 8) ? ((P & 64) ? 8 : 4) : NW; }
+  int BD() const { return ((P & 8) ? NW - staging_waves() : NW) * G; }   // consumers x G
   // P bit 5: one staged copy per channel (lane 63 of every 256-sample stripe
   // only feeds its neighbour, so a stripe yields 252 outputs); else four
   // shifted copies
