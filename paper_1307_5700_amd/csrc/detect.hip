@@ -76,7 +76,25 @@ __global__ __launch_bounds__(1024) void norm_kernel(const float* __restrict__ ou
   const double stt = N * (N * N - 1.0) / 12.0;
   const double b = stt > 0.0 ? st / stt : 0.0;
   const double a = (nout > 0 ? s1 / N : 0.0) - b * tbar;
-  double r2 = 0.0;
+  // Residual sum of squares from the same pass: (S2 - S1^2/N) - St^2/Stt.
+  // Kept when it is not small against S2, where its cancellation error stays
+  // far below the row's own rounding; otherwise (a large mean against the
+  // scatter, an exactly linear or constant row) the row is read again and
+  // the residuals summed directly.  The branch is uniform per workgroup.
+  double r2 = nout > 0 ? (s2 - s1 * s1 / N) - (stt > 0.0 ? st * st / stt : 0.0) : 0.0;
+  if (r2 > 1e-4 * s2) {
+    if (threadIdx.x == 0) {
+      NormDev nd;
+      nd.a = a;
+      nd.b = b;
+      nd.sigma = sqrt(r2 / N);
+      nd.degenerate = nd.sigma <= kDegenerateRtol * sqrt(s2 / N) ? 1 : 0;
+      nd.reserved = 0;
+      norm[d] = nd;
+    }
+    return;
+  }
+  r2 = 0.0;
   for (int64_t i = threadIdx.x; i < n4; i += 1024) {
     const float4 v = reinterpret_cast<const float4*>(row)[i];
     const double t = (double)(4 * i);

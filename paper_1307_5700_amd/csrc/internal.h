@@ -36,7 +36,7 @@ static_assert(sizeof(RfiHeader) <= 256, "header too large");
 struct RfiGeom {
   int64_t C, T, W, J, nspans, CG, ngroups;
   size_t off_hdr, off_fit, off_fit32, off_bsum, off_binterp, off_span, off_chunk, off_spart;
-  size_t off_flags, off_lcount, off_list, off_gflags, off_masked, off_cbits, off_gspan, total;
+  size_t off_flags, off_lcount, off_list, off_gflags, off_masked, off_cbits, total;
   int64_t JW;                // 32-bit words per channel of the chunk-flag bitmask
 };
 
@@ -70,7 +70,6 @@ inline RfiGeom rfi_geometry(int64_t C, int64_t T, int64_t W) {
   g.off_masked = o;   o = align256(o + size_t(C));
   g.JW = (g.J + 31) / 32;
   g.off_cbits = o;    o = align256(o + sizeof(uint32_t) * C * g.JW);
-  g.off_gspan = o;    o = align256(o + sizeof(int32_t) * (g.nspans + 1));
   g.total = o;
   return g;
 }
@@ -89,8 +88,7 @@ struct CleanView {
   const uint8_t* cflags;     // [C][J], bit1 = flagged after extension
   const uint8_t* gflags;     // [T]
   const uint32_t* cbits;     // [C][JW]: bit j%32 of word j/32 = chunk j flagged (extended)
-  const int32_t* gspan;      // [nspans+1]: flagged spectra before each 256-sample span
-  int64_t JW, nspans;
+  int64_t JW;
   int64_t J;
   uint32_t W;
   int32_t wshift;            // log2(W)

@@ -503,9 +503,7 @@ mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t 
     cv.gflags = reinterpret_cast<const uint8_t*>(stp + g.off_gflags);
     cv.J = g.J;
     cv.cbits = reinterpret_cast<const uint32_t*>(stp + g.off_cbits);
-    cv.gspan = reinterpret_cast<const int32_t*>(stp + g.off_gspan);
     cv.JW = g.JW;
-    cv.nspans = g.nspans;
     cv.W = (uint32_t)plan->desc.rfi.window;
     cv.wshift = 0;
     while ((1u << cv.wshift) < cv.W) ++cv.wshift;

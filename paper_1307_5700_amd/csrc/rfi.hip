@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
     const TIN* __restrict__ x, int64_t ld, int64_t C, int64_t T, int64_t W, int64_t J,
     const double* __restrict__ spart, int64_t ngroups, const double* __restrict__ fit,
     const int32_t* __restrict__ lcount, const int32_t* __restrict__ list,
-    RfiHeader* __restrict__ hdr, uint8_t* __restrict__ gflags, int32_t* __restrict__ span_count) {
+    RfiHeader* __restrict__ hdr, uint8_t* __restrict__ gflags) {
   __shared__ int wc[4];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -455,7 +455,6 @@ __global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
   __syncthreads();
   if (threadIdx.x == 0) {
     const int tot = wc[0] + wc[1] + wc[2] + wc[3];
-    span_count[blockIdx.x] = tot;
     if (tot) atomicAdd(&hdr->n_spec, (unsigned long long)tot);
   }
 }
@@ -477,29 +476,6 @@ __global__ __launch_bounds__(256) void rfi_chunk_bits_kernel(const uint8_t* __re
   cbits[i] = word;
 }
 
-__global__ __launch_bounds__(1024) void rfi_span_scan_kernel(int32_t* __restrict__ span_count,
-                                                             int64_t nspans) {
-  __shared__ int32_t sh[1024];
-  int32_t carry = 0;
-  for (int64_t base = 0; base < nspans; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const int32_t v = (i < nspans) ? span_count[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int32_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (i < nspans) span_count[i] = carry + sh[threadIdx.x] - v;    // exclusive, in place
-    const int32_t blk = sh[1023];
-    __syncthreads();
-    carry += blk;
-  }
-  if (threadIdx.x == 0) span_count[nspans] = carry;
-}
-
 template <typename TIN>
 hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiParamsDev& prm,
                         char* st, hipStream_t s) {
@@ -517,7 +493,6 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
   int32_t* list = reinterpret_cast<int32_t*>(st + g.off_list);
   RfiHeader* hdr = reinterpret_cast<RfiHeader*>(st + g.off_hdr);
   uint32_t* cbits = reinterpret_cast<uint32_t*>(st + g.off_cbits);
-  int32_t* gspan = reinterpret_cast<int32_t*>(st + g.off_gspan);
 
   hipLaunchKernelGGL(rfi_stats_kernel<TIN>, dim3((unsigned)g.nspans, (unsigned)g.ngroups),
                      dim3(256), 0, s, x, ld, g.C, g.T, g.nspans, g.CG, span_sum, spart);
@@ -536,10 +511,9 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
                      g.C, g.T, g.W, g.J, hdr, flags, lcount, list);
   hipLaunchKernelGGL(rfi_spectrum_flags_kernel<TIN>, dim3((unsigned)((g.T + 255) / 256)),
                      dim3(256), 0, s, x, ld, g.C, g.T, g.W, g.J, spart, g.ngroups, fit, lcount,
-                     list, hdr, gflags, gspan);
+                     list, hdr, gflags);
   hipLaunchKernelGGL(rfi_chunk_bits_kernel, dim3((unsigned)((g.C * g.JW + 255) / 256)), dim3(256), 0,
                      s, flags, g.C, g.J, g.JW, cbits);
-  hipLaunchKernelGGL(rfi_span_scan_kernel, dim3(1), dim3(1024), 0, s, gspan, g.nspans);
   return hipGetLastError();
 }
 
