@@ -2,8 +2,9 @@
 
 Plain, slow and obviously correct FP64 CPU implementation of what the GPU
 path computes: the cold-plasma delay table (Eq. 1), the thresholding RFI
-pass (Sec. 2.2.1), brute-force dedispersion (Sec. 2.2.2), per-DM detrending
-and normalisation (Sec. 2.2.3) and the n-sigma event threshold (Sec. 2.3).
+pass (Sec. 2.2.1), brute-force dedispersion (Sec. 2.2.2), the windowed
+median filter (Sec. 2.2.3, Eq. 2), per-DM detrending and normalisation
+(Sec. 2.2.3) and the n-sigma event threshold (Sec. 2.3).
 
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  It shares no code with the GPU path; the two meet only
@@ -11,8 +12,7 @@ through the seeded input generators, which hold none of the method's
 arithmetic.
 
 Readings of passages where the paper is silent or ambiguous are marked
-"Reading:" in the docstrings; each one is also listed with its alternatives
-in the design notes.
+"Reading:" in the docstrings.
 """
 from __future__ import annotations
 
@@ -389,6 +389,33 @@ def normalise(D: np.ndarray) -> NormResult:
     ok = ~degenerate
     z[ok] = r[ok] / sigma[ok, None]
     return NormResult(a, b, sigma, degenerate, z)
+
+
+# --------------------------------------------------------------------------
+# Windowed median filter, Sec. 2.2.3 (Eq. 2)
+# --------------------------------------------------------------------------
+
+def median_filter(D: np.ndarray, half_width: int) -> np.ndarray:
+    """Replace every sample of every DM's series by the median of the
+    2*half_width + 1 samples centred on it (Eq. 2 with the median as the
+    operation).
+
+    Reading: the window is 2h+1 samples; near the ends of a series the
+    missing neighbours repeat the end sample (indices clamped to the row), so
+    every window holds an odd count and the median is one of its samples.
+    The filter works on the samples of one call; it does not reach across
+    chunks of a stream.
+    """
+    D = np.asarray(D)
+    h = int(half_width)
+    if h < 0:
+        raise ValueError("half_width must be >= 0")
+    nd, N = D.shape
+    if N == 0 or h == 0:
+        return D.copy()
+    idx = np.clip(np.arange(N)[:, None] + np.arange(-h, h + 1)[None, :], 0, N - 1)
+    win = D[:, idx]                                  # [nd][N][2h+1]
+    return np.sort(win, axis=2)[:, :, h]
 
 
 # --------------------------------------------------------------------------
