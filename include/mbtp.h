@@ -241,6 +241,20 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in,
 mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout,
                            int64_t ld_out, mb_norm* d_norm, void* stream);
 
+/* Windowed median filter of a dedispersed plane (Sec. 2.2.3, Eq. 2): every
+ * sample of every row becomes the median of the 2*half_width + 1 samples
+ * centred on it; beyond a row's ends the end sample repeats, so every window
+ * has an odd count and the result is one of its samples (bit-exact against
+ * any correct median).  The filter sees only the samples of this call.
+ * d_in [nrows][ld_in] and d_out [nrows][ld_out] are FP32 device planes with
+ * ncols samples per row (ld_in, ld_out >= ncols); the caller owns both, and
+ * d_out must not overlap d_in.  half_width 0..16 (0 copies the plane).
+ * Asynchronous on stream.  Errors: MB_EINVAL for negative sizes, a
+ * half_width out of range, NULL planes, a leading dimension below ncols,
+ * overlapping planes or a plane beyond one launch (nothing is enqueued). */
+mb_status median_filter(const float* d_in, int64_t ld_in, float* d_out, int64_t ld_out,
+                        int32_t nrows, int64_t ncols, int32_t half_width, void* stream);
+
 /* ---- batched launch ------------------------------------------------------ */
 
 /* One beam chunk of a batch: the arguments of one dedisp_execute call. */

@@ -167,8 +167,13 @@ class Plan:
     # ---- dedispersion (Sec. 2.2.2) + normalisation (Sec. 2.2.3) ----
     def execute(self, x: torch.Tensor, rfi_state: torch.Tensor | None = None,
                 out: torch.Tensor | None = None, norm: torch.Tensor | None | bool = True,
-                beam: "Beam | None" = None, stream=None):
-        """Returns (out, norm, nout, sample0)."""
+                beam: "Beam | None" = None, stream=None, median: int = 0):
+        """Returns (out, norm, nout, sample0).
+
+        median > 0 runs the windowed median filter of half width `median`
+        between dedispersion and normalisation (Sec. 2.2.3): `out` then holds
+        the filtered plane, and the norm lines are those of the filtered
+        series."""
         T, ld = self._check_input(x)
         if out is None:
             seen = beam.position() if beam is not None else 0
@@ -179,9 +184,15 @@ class Plan:
         elif norm is False:
             norm = None
         info = L.ExecInfo()
+        raw = torch.empty_like(out) if median else out
         L.check(L.lib().dedisp_execute(self._h, beam._h if beam is not None else None, _ptr(x), T, ld,
-                                       _ptr(rfi_state), _ptr(out), out.stride(0), _ptr(norm),
-                                       ctypes.byref(info), _stream_ptr(stream)), "dedisp_execute")
+                                       _ptr(rfi_state), _ptr(raw), raw.stride(0),
+                                       _ptr(None if median else norm), ctypes.byref(info),
+                                       _stream_ptr(stream)), "dedisp_execute")
+        if median:
+            median_filter(raw, info.nout, median, out=out, stream=stream)
+            if norm is not None:
+                self.normalise(out, info.nout, norm, stream=stream)
         return out, norm, info.nout, info.sample0
 
     def normalise(self, out: torch.Tensor, nout: int, norm: torch.Tensor | None = None, stream=None):
@@ -224,6 +235,24 @@ class Plan:
     @staticmethod
     def peaks_to_host(peaks: torch.Tensor) -> np.ndarray:
         return peaks.cpu().numpy().view(PEAK_DTYPE)
+
+
+def median_filter(plane: torch.Tensor, ncols: int, half_width: int, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """Windowed median filter (Sec. 2.2.3, Eq. 2) of the first `ncols`
+    samples of every row of an FP32 device plane [rows][ld]: each sample
+    becomes the median of the 2*half_width + 1 samples centred on it, the end
+    samples repeating beyond the row's ends.  Returns `out` (a new plane of
+    the same shape when not given; it must not overlap `plane`)."""
+    if plane.dtype != torch.float32 or plane.dim() != 2 or plane.stride(1) != 1:
+        raise ValueError("plane must be a 2-D row-major float32 tensor")
+    if out is None:
+        out = torch.empty_like(plane)
+    if out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1 or out.shape[0] != plane.shape[0]:
+        raise ValueError("out must be a 2-D row-major float32 tensor with the plane's rows")
+    L.check(L.lib().median_filter(_ptr(plane), plane.stride(0), _ptr(out), out.stride(0), int(plane.shape[0]),
+                                  int(ncols), int(half_width), _stream_ptr(stream)), "median_filter")
+    return out
 
 
 def num_tilings() -> int:

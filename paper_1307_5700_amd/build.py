@@ -28,6 +28,7 @@ SOURCES = {
     "rfi.hip": [],
     "dedisp.hip": [],
     "detect.hip": [],
+    "median.hip": [],
     "mbtp.cpp": ["-x", "hip", "-ffp-contract=off"],
 }
 

@@ -193,6 +193,14 @@ struct PeakDev { int64_t sample; float snr; int32_t reserved; };
 hipError_t launch_norm(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
                        NormDev* norm, hipStream_t s);
 
+// Windowed median filter (median.hip): half widths 0..kMedianMaxHalf; one
+// workgroup per median_tile() outputs of a row.
+constexpr int kMedianMaxHalf = 16;
+int64_t median_tile();
+int64_t median_max_workgroups();
+hipError_t launch_median(const float* in, int64_t ld_in, float* out, int64_t ld_out, int32_t nrows,
+                         int64_t ncols, int32_t half_width, hipStream_t s);
+
 hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
                          const NormDev* norm, int64_t sample0, double nsigma,
                          double dm_start, double dm_step, CandDev* cands, int64_t capacity,

@@ -657,6 +657,27 @@ mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout
   return ok();
 }
 
+mb_status median_filter(const float* d_in, int64_t ld_in, float* d_out, int64_t ld_out, int32_t nrows,
+                        int64_t ncols, int32_t half_width, void* stream) {
+  if (nrows < 0 || ncols < 0) return fail(MB_EINVAL, "nrows and ncols must be >= 0");
+  if (half_width < 0 || half_width > kMedianMaxHalf)
+    return fail(MB_EINVAL, "half_width %d not in 0..%d", half_width, kMedianMaxHalf);
+  if (nrows == 0 || ncols == 0) return ok();
+  if (!d_in || !d_out) return fail(MB_EINVAL, "planes must not be NULL");
+  if (ld_in < ncols || ld_out < ncols) return fail(MB_EINVAL, "ld_in and ld_out must be >= ncols");
+  if (ncols > kMaxSamps) return fail(MB_EINVAL, "ncols %lld exceeds %lld", (long long)ncols, (long long)kMaxSamps);
+  const int64_t ntiles = (ncols + median_tile() - 1) / median_tile();
+  if (ntiles > median_max_workgroups() / nrows) return fail(MB_EINVAL, "plane too large for one launch");
+  // the two planes' spans must not intersect
+  const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in);
+  const uintptr_t i1 = i0 + sizeof(float) * (size_t)((nrows - 1) * ld_in + ncols);
+  const uintptr_t o0 = reinterpret_cast<uintptr_t>(d_out);
+  const uintptr_t o1 = o0 + sizeof(float) * (size_t)((nrows - 1) * ld_out + ncols);
+  if (i0 < o1 && o0 < i1) return fail(MB_EINVAL, "d_out must not overlap d_in");
+  HIP_TRY(launch_median(d_in, ld_in, d_out, ld_out, nrows, ncols, half_width, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MB_EINVAL, "plan and bytes must not be NULL");
   *bytes = detect_work_bytes(plan->desc.ndms);

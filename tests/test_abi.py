@@ -96,3 +96,19 @@ def test_null_plan_calls_rejected():
     assert lib.rfi_threshold(None, None, 10, 12, None, 0, None) == L.MB_EINVAL
     assert lib.detect_candidates(None, None, 0, 0, None, 0, 6.0, None, 0, None, None, None, 0, None) == L.MB_EINVAL
     assert lib.dedisp_plan_destroy(None) == L.MB_OK
+
+
+def test_median_filter_rejects_bad_arguments():
+    """Every rejection happens before anything is enqueued (no GPU here):
+    the pointers below are never dereferenced."""
+    L = _lib()
+    lib = L.lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    assert lib.median_filter(a, 100, b, 100, 4, 100, 17, None) == L.MB_EINVAL     # half width too big
+    assert lib.median_filter(a, 100, b, 100, 4, 100, -1, None) == L.MB_EINVAL
+    assert lib.median_filter(None, 100, b, 100, 4, 100, 2, None) == L.MB_EINVAL   # NULL plane
+    assert lib.median_filter(a, 99, b, 100, 4, 100, 2, None) == L.MB_EINVAL       # ld below ncols
+    assert lib.median_filter(a, 100, b, 100, -1, 100, 2, None) == L.MB_EINVAL
+    assert lib.median_filter(a, 100, ctypes.c_void_p((1 << 20) + 400 * 3), 100, 4, 100, 2, None) == L.MB_EINVAL  # overlap
+    assert lib.median_filter(None, 0, None, 0, 0, 100, 2, None) == L.MB_OK       # empty: nothing to do
+    assert lib.median_filter(None, 0, None, 0, 4, 0, 2, None) == L.MB_OK
