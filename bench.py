@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -60,17 +60,28 @@ def parse():
                          "known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
-                         "WRITE_SIZE) into profiles/dedisp_traffic.txt and exit")
+                         "WRITE_SIZE) into the workload's profiles/*_traffic.txt and exit")
     return ap.parse_args()
 
 
 CALIB_BYTES = 256 * 1024 * 1024
 
 
-def traffic_summary(fetch_csv: str, write_csv: str) -> None:
-    """HBM bytes per dedispersion launch from the PMC runs, each counter
-    scaled by what it reads for the calibration copy of known size."""
+# Kernels whose HBM traffic is summarised under profiles/: workload ->
+# (kernel name substring, summary file, sources hashed, description).
+TRAFFIC = {
+    "paper": ("dedisp_kernel", "dedisp_traffic.txt", ("dedisp.hip", "internal.h"),
+              "one dedisp_kernel launch, bench workload (1024 ch x 65536 samples x 640 DMs, f32, RFI on)"),
+    "median": ("median_kernel<2>", "median_traffic.txt", ("median.hip", "internal.h"),
+               "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
+}
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, workload: str) -> None:
+    """HBM bytes per launch of the workload's kernel from the PMC runs, each
+    counter scaled by what it reads for the calibration copy of known size."""
     import csv
+    kname, fname, srcs, desc = TRAFFIC[workload]
 
     def per_kernel(path, counter):
         vals = {}
@@ -78,7 +89,7 @@ def traffic_summary(fetch_csv: str, write_csv: str) -> None:
             if r["Counter_Name"] != counter:
                 continue
             name = r["Kernel_Name"]
-            key = "dedisp" if "dedisp_kernel" in name else ("copy" if "copyBuffer" in name else None)
+            key = "k" if kname in name else ("copy" if "copyBuffer" in name else None)
             if key:
                 vals.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
         return vals
@@ -89,26 +100,46 @@ def traffic_summary(fetch_csv: str, write_csv: str) -> None:
     # plan's small table upload is another)
     f_scale = CALIB_BYTES / float(np.max(f["copy"]))
     w_scale = CALIB_BYTES / float(np.max(w["copy"]))
-    fetch = float(np.mean(f["dedisp"])) * f_scale
-    write = float(np.mean(w["dedisp"])) * w_scale
-    path = os.path.join(ROOT, "profiles", "dedisp_traffic.txt")
+    fetch = float(np.mean(f["k"])) * f_scale
+    write = float(np.mean(w["k"])) * w_scale
+    path = os.path.join(ROOT, "profiles", fname)
+    wl = "" if workload == "paper" else f" --workload {workload}"
     with open(path, "w") as fh:
-        fh.write("# HBM traffic of one dedisp_kernel launch, bench workload "
-                 "(1024 ch x 65536 samples x 640 DMs, f32, RFI on)\n")
+        fh.write(f"# HBM traffic of {desc}\n")
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
             fh.write(f"# command: cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {ctr} --output-format csv "
-                     f"-d OUT -o bench -- python3 REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline "
+                     f"-d OUT -o bench -- python3 REPO/bench.py{wl} --steps 3 --warmup 1 --no-cpu-baseline "
                      f"--calib-copy\n")
-        fh.write("# then: python bench.py --traffic-from OUT_FETCH/bench_counter_collection.csv "
+        fh.write(f"# then: python bench.py{wl} --traffic-from OUT_FETCH/bench_counter_collection.csv "
                  "OUT_WRITE/bench_counter_collection.csv\n")
-        fh.write(f"kernel_source_hash={_kernel_hash()}\n")
+        fh.write(f"kernel_source_hash={_kernel_hash(srcs)}\n")
         fh.write(f"# counter reading of the {CALIB_BYTES >> 20} MiB calibration copy, KiB: fetch "
                  f"{np.max(f['copy']) / 1024:.0f}, write {np.max(w['copy']) / 1024:.0f}\n")
-        fh.write(f"# dedisp_kernel dispatches: {len(f['dedisp'])} (fetch), {len(w['dedisp'])} (write)\n")
+        fh.write(f"# {kname} dispatches: {len(f['k'])} (fetch), {len(w['k'])} (write)\n")
         fh.write(f"fetch_scale={f_scale:.4f}\nwrite_scale={w_scale:.4f}\n")
         fh.write(f"fetch_bytes={fetch:.0f}\nwrite_bytes={write:.0f}\n")
         fh.write(f"bytes_per_launch={fetch + write:.0f}\n")
     print(open(path).read())
+
+
+def _traffic(workload: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the kernel's current source (None otherwise)."""
+    kname, fname, srcs, _ = TRAFFIC[workload]
+    tf = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(tf):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(tf) if "=" in l and not l.startswith("#"))
+    return float(kv["bytes_per_launch"]) if kv.get("kernel_source_hash") == _kernel_hash(srcs) else None
+
+
+def _calib_copy():
+    import torch
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(beam, x, min_seconds: float = 10.0, max_reps: int = 8):
@@ -133,7 +164,7 @@ def cpu_baseline(beam, x, min_seconds: float = 10.0, max_reps: int = 8):
 def main():
     args = parse()
     if args.traffic_from:
-        traffic_summary(*args.traffic_from)
+        traffic_summary(*args.traffic_from, args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (sharding by beam, "
@@ -142,7 +173,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     if args.workload != "paper":
-        res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision}[args.workload](args)
+        res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
+               "median": bench_median}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     from paper_1307_5700_amd import api as A
@@ -192,20 +224,8 @@ def main():
     achieved = adds / (k_ms * 1e-3) / 1e12
 
     if args.calib_copy:
-        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-
-    # HBM bytes per launch from the committed PMC summary, if it was taken on
-    # this kernel source (null otherwise)
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "dedisp_traffic.txt")
-    if os.path.exists(tf):
-        kv = dict(l.strip().split("=", 1) for l in open(tf) if "=" in l and not l.startswith("#"))
-        if kv.get("kernel_source_hash") == _kernel_hash():
-            traffic = float(kv["bytes_per_launch"])
+        _calib_copy()
+    traffic = _traffic("paper")
 
     res = {
         "metric": "DM-trial samples/s",
@@ -407,10 +427,76 @@ def bench_precision(args):
     return _line(per[best]["value"], per[best]["ms"] * 1e-3, args, best, cfg, {"storage": per})
 
 
-def _kernel_hash() -> str:
+def bench_median(args):
+    """The windowed median filter (Sec. 2.2.3, Eq. 2) on the paper-shaped
+    dedispersed plane (640 DMs x 59434 outputs, FP32, RFI on), half width 2
+    (5-sample window); other half widths for context.  One step = one filter
+    pass over the plane; HIP events on the stream time the kernel."""
+    import torch
+    import oracle
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    beam = synth.paper_beam()
+    plan = A.Plan.from_beam(beam)
+    x = torch.from_numpy(synth.render(beam, plan.delays())).cuda()
+    out, _, nout, _ = plan.execute(x, rfi_state=plan.rfi_threshold(x), norm=False)
+    del x
+    filt = torch.empty_like(out)
+    stream = torch.cuda.current_stream()
+    tiles = (nout + 1023) // 1024
+    per = {}
+    for h in (2, 1, 4, 8, 16):
+        def step():
+            A.median_filter(out, nout, h, out=filt)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        k_ms = e0.elapsed_time(e1) / args.steps
+        # algorithmic bytes: each sample read and written once, plus each tile's halo
+        nbytes = plan.ndms * (nout * 8 + tiles * 2 * h * 4)
+        per[h] = {"ms_per_step": dt * 1e3, "kernel_ms": k_ms, "hbm_gbs": nbytes / (k_ms * 1e-3) / 1e9,
+                  "bytes_per_launch": nbytes}
+    main = per[2]
+    if args.calib_copy:
+        _calib_copy()
+    # CPU baseline: the oracle on a bounded sample of rows
+    rows = 16
+    host = out[:rows, :nout].cpu().numpy()
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.median_filter(host, 2)
+        reps += 1
+        if time.perf_counter() - t0 > min(args.cpu_seconds, 10.0):
+            break
+    cpu_s = (time.perf_counter() - t0) / reps
+    cfg = {"workload": "median_filter_640dm_59434samp_f32_h2", "ndms": plan.ndms, "nout": nout,
+           "half_width": 2, "window": 5, "parallelism": "none"}
+    extra = {"roofline": {"bound": "hbm", "kernel": "median_kernel<2>", "achieved": main["hbm_gbs"],
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": main["hbm_gbs"] / PEAK_HBM_GBS,
+                          "traffic": _traffic("median")},
+             "half_widths": per}
+    if not args.no_cpu_baseline:
+        extra["cpu_baseline"] = {"value": rows * nout / cpu_s, "unit": "DM-trial samples/s", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": f"{rows} rows x {nout} samples, h = 2, {reps} passes in "
+                                           f"{cpu_s * reps:.1f} s (numpy sort, one thread)"}
+    return _line(plan.ndms * nout / (main["ms_per_step"] * 1e-3), main["ms_per_step"] * 1e-3, args, "f32",
+                 cfg, extra)
+
+
+def _kernel_hash(srcs=("dedisp.hip", "internal.h")) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("dedisp.hip", "internal.h"):
+    for f in srcs:
         h.update(open(os.path.join(ROOT, "paper_1307_5700_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -86,3 +86,30 @@ def test_one_sided_spectrum_threshold_misses_gap():
     assert r.spectrum_flags[4000] and r.spectrum_flags[4001]
     one_sided = r.spectrum_means > oracle.RfiParams().k_spec * r.sigma / math.sqrt(256)
     assert not one_sided[4000]
+
+
+def test_median_mutants_fail_pins():
+    """Slips in the median filter: the rank one off, the ends wrapping round
+    instead of repeating, an even window, the window not centred."""
+    import sys
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_median import _brute
+
+    def mutant(D, h, rank=None, mode="clip", lo=None, hi=None):
+        nd, N = D.shape
+        lo = -h if lo is None else lo
+        hi = h if hi is None else hi
+        idx = np.arange(N)[:, None] + np.arange(lo, hi + 1)[None, :]
+        idx = np.clip(idx, 0, N - 1) if mode == "clip" else idx % N
+        w = np.sort(D[:, idx], axis=2)
+        return w[:, :, h if rank is None else rank]
+
+    rng = np.random.default_rng(31)
+    D = rng.standard_normal((3, 40)).astype(np.float32)
+    h = 2
+    ref = _brute(D, h)
+    assert np.array_equal(oracle.median_filter(D, h), ref)
+    for name, m in {"rank_low": mutant(D, h, rank=h - 1), "rank_high": mutant(D, h, rank=h + 1),
+                    "wrap_ends": mutant(D, h, mode="wrap"), "even_window": mutant(D, h, lo=-h, hi=h - 1),
+                    "shifted_window": mutant(D, h, lo=-h + 1, hi=h + 1)}.items():
+        assert not np.array_equal(m, ref), name
