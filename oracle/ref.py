@@ -4,7 +4,8 @@ Plain, slow and obviously correct FP64 CPU implementation of what the GPU
 path computes: the cold-plasma delay table (Eq. 1), the thresholding RFI
 pass (Sec. 2.2.1), brute-force dedispersion (Sec. 2.2.2), the windowed
 median filter (Sec. 2.2.3, Eq. 2), per-DM detrending and normalisation
-(Sec. 2.2.3) and the n-sigma event threshold (Sec. 2.3).
+(Sec. 2.2.3), the n-sigma event threshold (Sec. 2.3) and the data
+writer's mu-law codec (Sec. 2.4, Eq. 5).
 
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  It shares no code with the GPU path; the two meet only
@@ -416,6 +417,48 @@ def median_filter(D: np.ndarray, half_width: int) -> np.ndarray:
     idx = np.clip(np.arange(N)[:, None] + np.arange(-h, h + 1)[None, :], 0, N - 1)
     win = D[:, idx]                                  # [nd][N][2h+1]
     return np.sort(win, axis=2)[:, :, h]
+
+
+# --------------------------------------------------------------------------
+# mu-law codec of the data writer, Sec. 2.4 (Eq. 5)
+# --------------------------------------------------------------------------
+
+MULAW_LEVELS = 255     # 8-bit codes of a power series
+
+
+def mulaw_levels(x: np.ndarray, mu: float):
+    """Eq. (5) as a fraction of the code range: v = Q * log(1 + mu*x/X) /
+    log(1 + mu) per sample of each row, X the row's largest |x|, Q = 255.
+    Returns (v in FP64, X per row).
+
+    Reading: the series of Eq. (5) is one channel's row of the buffer, so X
+    is that row's maximum; power samples are non-negative and a negative
+    value (none occur in a power series) counts as 0; a row of zeros has
+    X = 0 and v = 0."""
+    x = np.asarray(x, dtype=np.float32)
+    X = np.max(np.abs(x), axis=1) if x.shape[1] else np.zeros(x.shape[0], np.float32)
+    xd = np.maximum(x.astype(np.float64), 0.0)
+    Xd = X.astype(np.float64)[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = np.where(Xd > 0, MULAW_LEVELS * np.log1p(float(mu) * xd / Xd) / math.log1p(float(mu)), 0.0)
+    return v, X
+
+
+def mulaw_encode(x: np.ndarray, mu: float = 255.0):
+    """8-bit mu-law codes of an FP32 power plane [rows][T] and the row
+    maxima needed to decode them.
+
+    Reading: the code is the nearest level, floor(v + 0.5), taken in FP64."""
+    v, X = mulaw_levels(x, mu)
+    return np.floor(v + 0.5).astype(np.uint8), X
+
+
+def mulaw_decode(codes: np.ndarray, X: np.ndarray, mu: float = 255.0) -> np.ndarray:
+    """Inverse of Eq. (5) at the code levels: x = X/mu * ((1+mu)^(q/255) - 1),
+    rounded to FP32."""
+    q = np.asarray(codes, dtype=np.float64)
+    Xd = np.asarray(X, dtype=np.float64)[:, None]
+    return (Xd / float(mu) * np.expm1(q / MULAW_LEVELS * math.log1p(float(mu)))).astype(np.float32)
 
 
 # --------------------------------------------------------------------------

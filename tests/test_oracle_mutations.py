@@ -113,3 +113,25 @@ def test_median_mutants_fail_pins():
                     "wrap_ends": mutant(D, h, mode="wrap"), "even_window": mutant(D, h, lo=-h, hi=h - 1),
                     "shifted_window": mutant(D, h, lo=-h + 1, hi=h + 1)}.items():
         assert not np.array_equal(m, ref), name
+
+
+def test_mulaw_mutants_fail_pins():
+    """Slips in the mu-law codec: floor instead of nearest, the row mean for
+    X, log(mu) in the denominator, 256 levels, mu applied twice (at mu = 15,
+    where log(mu) and log(1 + mu) differ by 2.4 %)."""
+    X, mu = 37.5, 15.0
+    ks = np.array([0, 1, 2, 17, 100, 200, 254, 255], np.float64)
+    xs = np.concatenate([[X], X / mu * np.expm1(ks / 255.0 * math.log1p(mu))]).astype(np.float32)[None, :]
+    good, _ = oracle.mulaw_encode(xs, mu)
+    assert list(good[0, 1:]) == ks.astype(int).tolist()
+    xd = xs.astype(np.float64)
+    Xm = np.max(xd)
+    mutants = {
+        "floor": np.floor(255 * np.log1p(mu * xd / Xm) / math.log1p(mu)),
+        "mean_for_X": np.floor(255 * np.log1p(mu * xd / xd.mean()) / math.log1p(mu) + 0.5),
+        "log_mu": np.floor(255 * np.log1p(mu * xd / Xm) / math.log(mu) + 0.5),
+        "levels_256": np.floor(256 * np.log1p(mu * xd / Xm) / math.log1p(mu) + 0.5),
+        "mu_twice": np.floor(255 * np.log1p(mu * mu * xd / Xm) / math.log1p(mu * mu) + 0.5),
+    }
+    for name, m in mutants.items():
+        assert not np.array_equal(m, good.astype(np.float64)), name
