@@ -255,6 +255,23 @@ mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout
 mb_status median_filter(const float* d_in, int64_t ld_in, float* d_out, int64_t ld_out,
                         int32_t nrows, int64_t ncols, int32_t half_width, void* stream);
 
+/* mu-law codec of the data writer (Sec. 2.4, Eq. 5) for FP32 power planes.
+ * mulaw_encode: for every row of d_in [nrows][ld_in] (ncols samples, ld_in
+ * >= ncols) X = the row's largest |x| goes to d_xmax[row], and every sample
+ * to the 8-bit code q = floor(255 * log1p(mu * x / X) / log1p(mu) + 1/2)
+ * in d_codes [nrows][ld_codes] (x < 0 counts as 0; a row of zeros gives
+ * X = 0 and codes 0).  The code is taken in FP64, each operation rounded on
+ * its own.  mulaw_decode: x = X / mu * expm1(q / 255 * log1p(mu)), FP64,
+ * rounded to FP32, into d_out [nrows][ld_out].  mu finite and > 0 (255 as
+ * in G.711).  Device planes owned by the caller; outputs must not overlap
+ * inputs.  Asynchronous on stream.  Errors: MB_EINVAL for negative sizes,
+ * a bad mu, NULL or overlapping planes, a leading dimension below ncols or a
+ * plane beyond one launch (nothing is enqueued). */
+mb_status mulaw_encode(const float* d_in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                       uint8_t* d_codes, int64_t ld_codes, float* d_xmax, void* stream);
+mb_status mulaw_decode(const uint8_t* d_codes, int64_t ld_codes, const float* d_xmax, int32_t nrows,
+                       int64_t ncols, float mu, float* d_out, int64_t ld_out, void* stream);
+
 /* ---- batched launch ------------------------------------------------------ */
 
 /* One beam chunk of a batch: the arguments of one dedisp_execute call. */

@@ -255,6 +255,35 @@ def median_filter(plane: torch.Tensor, ncols: int, half_width: int, out: torch.T
     return out
 
 
+def mulaw_encode(x: torch.Tensor, ncols: int, mu: float = 255.0, codes: torch.Tensor | None = None,
+                 xmax: torch.Tensor | None = None, stream=None):
+    """mu-law codes (Sec. 2.4, Eq. 5) of the first `ncols` samples of every
+    row of an FP32 device plane [rows][ld]: returns (codes uint8 [rows][ld],
+    xmax float32 [rows])."""
+    if x.dtype != torch.float32 or x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("x must be a 2-D row-major float32 tensor")
+    codes = torch.empty(x.shape, dtype=torch.uint8, device=x.device) if codes is None else codes
+    xmax = torch.empty(x.shape[0], dtype=torch.float32, device=x.device) if xmax is None else xmax
+    if codes.dtype != torch.uint8 or codes.dim() != 2 or codes.stride(1) != 1 or xmax.dtype != torch.float32:
+        raise ValueError("codes must be a 2-D row-major uint8 tensor and xmax float32")
+    L.check(L.lib().mulaw_encode(_ptr(x), x.stride(0), int(x.shape[0]), int(ncols), float(mu), _ptr(codes),
+                                 codes.stride(0), _ptr(xmax), _stream_ptr(stream)), "mulaw_encode")
+    return codes, xmax
+
+
+def mulaw_decode(codes: torch.Tensor, xmax: torch.Tensor, ncols: int, mu: float = 255.0,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """FP32 values of mu-law codes (the inverse map of Eq. 5)."""
+    if codes.dtype != torch.uint8 or codes.dim() != 2 or codes.stride(1) != 1:
+        raise ValueError("codes must be a 2-D row-major uint8 tensor")
+    out = torch.empty(codes.shape, dtype=torch.float32, device=codes.device) if out is None else out
+    if out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a 2-D row-major float32 tensor")
+    L.check(L.lib().mulaw_decode(_ptr(codes), codes.stride(0), _ptr(xmax), int(codes.shape[0]), int(ncols),
+                                 float(mu), _ptr(out), out.stride(0), _stream_ptr(stream)), "mulaw_decode")
+    return out
+
+
 def num_tilings() -> int:
     """Number of compiled dedispersion tilings (valid tile_hint: 1..n)."""
     n = ctypes.c_int32()

@@ -29,6 +29,7 @@ SOURCES = {
     "dedisp.hip": [],
     "detect.hip": [],
     "median.hip": [],
+    "mulaw.hip": [],
     "mbtp.cpp": ["-x", "hip", "-ffp-contract=off"],
 }
 

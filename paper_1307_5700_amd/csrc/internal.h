@@ -201,6 +201,12 @@ int64_t median_max_workgroups();
 hipError_t launch_median(const float* in, int64_t ld_in, float* out, int64_t ld_out, int32_t nrows,
                          int64_t ncols, int32_t half_width, hipStream_t s);
 
+// mu-law codec of the data writer (mulaw.hip).
+hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                               uint8_t* codes, int64_t ld_codes, float* xmax, hipStream_t s);
+hipError_t launch_mulaw_decode(const uint8_t* codes, int64_t ld_codes, const float* xmax, int32_t nrows,
+                               int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s);
+
 hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
                          const NormDev* norm, int64_t sample0, double nsigma,
                          double dm_start, double dm_step, CandDev* cands, int64_t capacity,

@@ -112,3 +112,18 @@ def test_median_filter_rejects_bad_arguments():
     assert lib.median_filter(a, 100, ctypes.c_void_p((1 << 20) + 400 * 3), 100, 4, 100, 2, None) == L.MB_EINVAL  # overlap
     assert lib.median_filter(None, 0, None, 0, 0, 100, 2, None) == L.MB_OK       # empty: nothing to do
     assert lib.median_filter(None, 0, None, 0, 4, 0, 2, None) == L.MB_OK
+
+
+def test_mulaw_rejects_bad_arguments():
+    L = _lib()
+    lib = L.lib()
+    a, b, x = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 34)
+    assert lib.mulaw_encode(a, 100, 4, 100, 0.0, b, 100, x, None) == L.MB_EINVAL           # mu <= 0
+    assert lib.mulaw_encode(a, 100, 4, 100, float("inf"), b, 100, x, None) == L.MB_EINVAL
+    assert lib.mulaw_encode(a, 100, 4, 100, 255.0, b, 100, None, None) == L.MB_EINVAL      # no xmax
+    assert lib.mulaw_encode(a, 99, 4, 100, 255.0, b, 100, x, None) == L.MB_EINVAL          # ld < ncols
+    assert lib.mulaw_encode(a, 100, 4, 100, 255.0, ctypes.c_void_p((1 << 20) + 8), 100, x, None) == L.MB_EINVAL
+    assert lib.mulaw_decode(b, 100, x, 4, 100, 255.0, None, 100, None) == L.MB_EINVAL      # NULL output
+    assert lib.mulaw_decode(b, 100, x, -1, 100, 255.0, a, 100, None) == L.MB_EINVAL
+    assert lib.mulaw_encode(None, 0, 0, 100, 255.0, None, 0, None, None) == L.MB_OK        # no rows
+    assert lib.mulaw_decode(None, 0, None, 4, 0, 255.0, None, 0, None) == L.MB_OK
