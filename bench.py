@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median", "mulaw"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -74,6 +74,8 @@ TRAFFIC = {
               "one dedisp_kernel launch, bench workload (1024 ch x 65536 samples x 640 DMs, f32, RFI on)"),
     "median": ("median_kernel<2>", "median_traffic.txt", ("median.hip", "internal.h"),
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
+    "mulaw": ("mulaw_encode_kernel", "mulaw_traffic.txt", ("mulaw.hip", "internal.h"),
+              "one mulaw_encode_kernel launch, mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
 }
 
 
@@ -174,7 +176,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "paper":
         res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
-               "median": bench_median}[args.workload](args)
+               "median": bench_median, "mulaw": bench_mulaw}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     from paper_1307_5700_amd import api as A
@@ -491,6 +493,69 @@ def bench_median(args):
                                            f"{cpu_s * reps:.1f} s (numpy sort, one thread)"}
     return _line(plan.ndms * nout / (main["ms_per_step"] * 1e-3), main["ms_per_step"] * 1e-3, args, "f32",
                  cfg, extra)
+
+
+def bench_mulaw(args):
+    """The data writer's mu-law codec (Sec. 2.4, Eq. 5) on the paper-shaped
+    FP32 power chunk (1024 channels x 65536 samples), mu = 255: one step =
+    one encode of the chunk to 8-bit codes (the buffer the writer would dump);
+    the decode is timed alongside.  HIP events on the stream time the
+    kernels."""
+    import torch
+    import oracle
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    beam = synth.paper_beam()
+    plan = A.Plan.from_beam(beam)
+    xh = synth.render(beam, plan.delays())
+    x = torch.from_numpy(xh).cuda()
+    C, T = x.shape
+    codes, xmax = A.mulaw_encode(x, T)
+    dec = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, e0.elapsed_time(e1) / args.steps
+
+    dt, k_ms = timed(lambda: A.mulaw_encode(x, T, codes=codes, xmax=xmax))
+    ddt, dk_ms = timed(lambda: A.mulaw_decode(codes, xmax, T, out=dec))
+    if args.calib_copy:
+        _calib_copy()
+    enc_bytes = C * T * (4 + 1)            # read the plane once, write the codes
+    dec_bytes = C * T * (1 + 4)
+    rows = 64                              # CPU baseline sample
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.mulaw_encode(xh[:rows], 255.0)
+        reps += 1
+        if time.perf_counter() - t0 > min(args.cpu_seconds, 10.0):
+            break
+    cpu_s = (time.perf_counter() - t0) / reps
+    cfg = {"workload": "mulaw_encode_1024ch_65536samp_f32_mu255", "nchans": C, "nsamps": T, "mu": 255.0,
+           "code_bits": 8, "parallelism": "none"}
+    extra = {"roofline": {"bound": "hbm", "kernel": "mulaw_encode_kernel", "achieved": enc_bytes / (k_ms * 1e-3) / 1e9,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": enc_bytes / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic("mulaw")},
+             "encode_kernel_ms": k_ms,
+             "decode": {"ms_per_step": ddt * 1e3, "kernel_ms": dk_ms, "hbm_gbs": dec_bytes / (dk_ms * 1e-3) / 1e9}}
+    if not args.no_cpu_baseline:
+        extra["cpu_baseline"] = {"value": rows * T / cpu_s, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"encode of {rows} channels x {T} samples, {reps} passes in "
+                                           f"{cpu_s * reps:.1f} s (numpy, one thread)"}
+    res = _line(C * T / dt, dt, args, "f32", cfg, extra)
+    res["metric"] = res["unit"] = "samples/s"
+    return res
 
 
 def _kernel_hash(srcs=("dedisp.hip", "internal.h")) -> str:
