@@ -260,8 +260,9 @@ mb_status median_filter(const float* d_in, int64_t ld_in, float* d_out, int64_t 
  * >= ncols) X = the row's largest |x| goes to d_xmax[row], and every sample
  * to the 8-bit code q = floor(255 * log1p(mu * x / X) / log1p(mu) + 1/2)
  * in d_codes [nrows][ld_codes] (x < 0 counts as 0; a row of zeros gives
- * X = 0 and codes 0).  The code is taken in FP64, each operation rounded on
- * its own.  mulaw_decode: x = X / mu * expm1(q / 255 * log1p(mu)), FP64,
+ * X = 0 and codes 0).  The code is the number of level boundaries
+ * X/mu * expm1((k - 1/2)/255 * log1p(mu)), k = 1..255, formed in FP64, that
+ * x reaches.  mulaw_decode: x = X / mu * expm1(q / 255 * log1p(mu)), FP64,
  * rounded to FP32, into d_out [nrows][ld_out].  mu finite and > 0 (255 as
  * in G.711).  Device planes owned by the caller; outputs must not overlap
  * inputs.  Asynchronous on stream.  Errors: MB_EINVAL for negative sizes,

@@ -2,12 +2,17 @@
 //
 // Encode: one 1024-thread workgroup per row of an FP32 power plane.  The
 // row's largest |x| (X) comes from one pass of 16-byte loads and a block
-// max; a second pass (mostly from L2) maps every sample to its 8-bit code
+// max.  The code of a sample is the nearest level of Eq. (5),
 //   q = floor(255 * log1p(mu * x / X) / log1p(mu) + 1/2),  x < 0 taken as 0,
-// in FP64 with each operation rounded on its own (no contraction), so the
-// code, a decision taken in floating point, follows the same steps
-// wherever it is computed.  X is stored per row for the decoder.
-// Decode: x = X / mu * expm1(q / 255 * log1p(mu)), FP64, rounded to FP32.
+// i.e. the number of level boundaries b_k = X/mu * expm1((k - 1/2)/255 *
+// log1p(mu)), k = 1..255, that x reaches.  The 255 boundaries are formed in
+// FP64 once per row and rounded up to FP32: x is an FP32 value, so x >= b_k
+// exactly when x reaches the rounded-up boundary.  A sample's code is then
+// an FP32 log estimate corrected by one comparison on each side against the
+// boundaries in LDS, which makes it exact whatever the estimate's error (at
+// most one level).  X is stored per row for the decoder.
+// Decode: x = X / mu * expm1(q / 255 * log1p(mu)), FP64, rounded to FP32;
+// the 256 values of a row are formed once per workgroup in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,20 +23,14 @@ namespace mbtp {
 namespace {
 
 constexpr double kLevels = 255.0;
-
-__device__ inline uint8_t code_of(float x, double mu, double Xd, double l1mu) {
-  if (!(Xd > 0.0)) return 0;
-  const double xd = x > 0.0f ? (double)x : 0.0;
-  const double t = __ddiv_rn(__dmul_rn(mu, xd), Xd);
-  const double v = __ddiv_rn(__dmul_rn(kLevels, log1p(t)), l1mu);
-  return (uint8_t)floor(__dadd_rn(v, 0.5));
-}
+constexpr int kDecodeTile = 8192;     // samples per decode workgroup (one 256-entry table each)
 
 __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restrict__ in, int64_t ld_in,
                                                             int64_t ncols, double mu, double l1mu,
                                                             uint8_t* __restrict__ codes, int64_t ld_codes,
                                                             float* __restrict__ xmax, int vin, int vout) {
   __shared__ float sh[16];
+  __shared__ float bound[257];           // bound[k]: least FP32 x with code >= k (k = 1..255)
   const int64_t row = blockIdx.x;
   const float* r = in + row * ld_in;
   uint8_t* c = codes + row * ld_codes;
@@ -51,37 +50,63 @@ __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restr
 #pragma unroll
   for (int k = 0; k < 16; ++k) X = fmaxf(X, sh[k]);
   if (tid == 0) xmax[row] = X;
-  const double Xd = X;
+  if (tid >= 1 && tid <= 255) {
+    const double b = __dmul_rn(__ddiv_rn((double)X, mu),
+                               expm1(__dmul_rn(((double)tid - 0.5) / kLevels, l1mu)));
+    float f = (float)b;
+    if ((double)f < b) f = nextafterf(f, INFINITY);
+    bound[tid] = f;
+  } else if (tid == 0) {
+    bound[0] = -INFINITY;
+  } else if (tid == 256) {
+    bound[256] = INFINITY;
+  }
+  __syncthreads();
+  if (!(X > 0.0f)) {
+    // a row of zeros: every code is 0
+    for (int64_t i = tid; i < ncols; i += 1024) c[i] = 0;
+    return;
+  }
+  const float s = (float)(mu / (double)X), inv = (float)(kLevels / l1mu);
+  auto code = [&](float x) -> uint32_t {
+    const float xc = fmaxf(x, 0.0f);
+    int q = (int)(inv * __logf(1.0f + s * xc) + 0.5f);
+    q = q < 0 ? 0 : (q > 255 ? 255 : q);
+    q += (xc >= bound[q + 1]) ? 1 : 0;
+    q -= (xc < bound[q]) ? 1 : 0;
+    return (uint32_t)q;
+  };
   const int64_t q4 = (vin && vout) ? ncols / 4 : 0;
   for (int64_t i = tid; i < q4; i += 1024) {
     const float4 v = reinterpret_cast<const float4*>(r)[i];
-    const uint32_t w = (uint32_t)code_of(v.x, mu, Xd, l1mu) | ((uint32_t)code_of(v.y, mu, Xd, l1mu) << 8) |
-                       ((uint32_t)code_of(v.z, mu, Xd, l1mu) << 16) | ((uint32_t)code_of(v.w, mu, Xd, l1mu) << 24);
-    reinterpret_cast<uint32_t*>(c)[i] = w;
+    reinterpret_cast<uint32_t*>(c)[i] = code(v.x) | (code(v.y) << 8) | (code(v.z) << 16) | (code(v.w) << 24);
   }
-  for (int64_t i = 4 * q4 + tid; i < ncols; i += 1024) c[i] = code_of(r[i], mu, Xd, l1mu);
-}
-
-__device__ inline float value_of(uint8_t q, double scale, double step) {
-  return (float)__dmul_rn(scale, expm1(__dmul_rn((double)q / kLevels, step)));
+  for (int64_t i = 4 * q4 + tid; i < ncols; i += 1024) c[i] = (uint8_t)code(r[i]);
 }
 
 __global__ __launch_bounds__(256) void mulaw_decode_kernel(const uint8_t* __restrict__ codes, int64_t ld_codes,
                                                            const float* __restrict__ xmax, int64_t ncols,
                                                            int64_t ntiles, double mu, double l1mu,
                                                            float* __restrict__ out, int64_t ld_out, int vec) {
+  __shared__ float lut[256];
   const int64_t row = blockIdx.x / ntiles;
-  const int64_t m = (blockIdx.x % ntiles) * 1024 + 4 * threadIdx.x;
+  const int64_t base = (blockIdx.x % ntiles) * kDecodeTile;
   const uint8_t* c = codes + row * ld_codes;
   float* o = out + row * ld_out;
   const double scale = __ddiv_rn((double)xmax[row], mu);
-  if (vec && m + 3 < ncols) {
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m);
-    *reinterpret_cast<float4*>(o + m) = make_float4(value_of(w & 0xffu, scale, l1mu), value_of((w >> 8) & 0xffu, scale, l1mu),
-                                                    value_of((w >> 16) & 0xffu, scale, l1mu), value_of(w >> 24, scale, l1mu));
-  } else {
-    for (int j = 0; j < 4; ++j)
-      if (m + j < ncols) o[m + j] = value_of(c[m + j], scale, l1mu);
+  lut[threadIdx.x] = (float)__dmul_rn(scale, expm1(__dmul_rn((double)threadIdx.x / kLevels, l1mu)));
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < kDecodeTile / 1024; ++j) {
+    const int64_t m = base + 1024 * j + 4 * threadIdx.x;
+    if (vec && m + 3 < ncols) {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m);
+      *reinterpret_cast<float4*>(o + m) = make_float4(lut[w & 0xffu], lut[(w >> 8) & 0xffu],
+                                                      lut[(w >> 16) & 0xffu], lut[w >> 24]);
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (m + q < ncols) o[m + q] = lut[c[m + q]];
+    }
   }
 }
 
@@ -98,7 +123,7 @@ hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, in
 
 hipError_t launch_mulaw_decode(const uint8_t* codes, int64_t ld_codes, const float* xmax, int32_t nrows,
                                int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s) {
-  const int64_t ntiles = (ncols + 1023) / 1024;
+  const int64_t ntiles = (ncols + kDecodeTile - 1) / kDecodeTile;
   const int vec = (reinterpret_cast<uintptr_t>(codes) % 4 == 0 && ld_codes % 4 == 0 &&
                    reinterpret_cast<uintptr_t>(out) % 16 == 0 && ld_out % 4 == 0) ? 1 : 0;
   hipLaunchKernelGGL(mulaw_decode_kernel, dim3((unsigned)(ntiles * nrows)), dim3(256), 0, s, codes, ld_codes,
