@@ -1,7 +1,8 @@
 """Oracle for the multibeam transient hot path (test infrastructure only).
 
 Plain, slow and obviously correct FP64 CPU implementation of what the GPU
-path computes: the cold-plasma delay table (Eq. 1), the thresholding RFI
+path computes: the power of beamformed voltages (Sec. 2.2), the cold-plasma
+delay table (Eq. 1), the thresholding RFI
 pass (Sec. 2.2.1), brute-force dedispersion (Sec. 2.2.2), the windowed
 median filter (Sec. 2.2.3, Eq. 2), per-DM detrending and normalisation
 (Sec. 2.2.3), the n-sigma event threshold (Sec. 2.3) and the data
@@ -390,6 +391,26 @@ def normalise(D: np.ndarray) -> NormResult:
     ok = ~degenerate
     z[ok] = r[ok] / sigma[ok, None]
     return NormResult(a, b, sigma, degenerate, z)
+
+
+# --------------------------------------------------------------------------
+# Power calculation from beamformed voltages, Sec. 2.2
+# --------------------------------------------------------------------------
+
+def power_from_voltages(v: np.ndarray) -> np.ndarray:
+    """Channelised power of 16-bit complex voltages: v [T][C][2] int16
+    (re, im) spectra in time order -> FP32 power [C][T] = re^2 + im^2.
+
+    Reading: the beamformer's samples arrive one spectrum per time step
+    (time-major) and the pipeline's buffers are channel rows, so the step
+    also transposes; the sum of squares is exact in integers and rounded
+    once to FP32."""
+    v = np.asarray(v)
+    if v.dtype != np.int16 or v.ndim != 3 or v.shape[2] != 2:
+        raise ValueError("voltages must be int16 [T][C][2]")
+    re = v[:, :, 0].astype(np.int64)
+    im = v[:, :, 1].astype(np.int64)
+    return np.ascontiguousarray((re * re + im * im).astype(np.float32).T)
 
 
 # --------------------------------------------------------------------------
