@@ -398,19 +398,19 @@ def normalise(D: np.ndarray) -> NormResult:
 # --------------------------------------------------------------------------
 
 def power_from_voltages(v: np.ndarray) -> np.ndarray:
-    """Channelised power of 16-bit complex voltages: v [T][C][2] int16
-    (re, im) spectra in time order -> FP32 power [C][T] = re^2 + im^2.
+    """Channelised power of 16-bit complex voltages (Sec. 2.2): v [C][T][2]
+    int16 (re, im) -> FP32 power [C][T] = re^2 + im^2.
 
-    Reading: the beamformer's samples arrive one spectrum per time step
-    (time-major) and the pipeline's buffers are channel rows, so the step
-    also transposes; the sum of squares is exact in integers and rounded
-    once to FP32."""
+    Reading: the beamformer's heaps are in beam/channel/time order and the
+    receiver lays a beam's buffer out in that order (Sec. 2.1), so the step
+    is elementwise over channel rows; the sum of squares is exact in
+    integers (at most 2^31) and rounded once to FP32."""
     v = np.asarray(v)
     if v.dtype != np.int16 or v.ndim != 3 or v.shape[2] != 2:
-        raise ValueError("voltages must be int16 [T][C][2]")
+        raise ValueError("voltages must be int16 [C][T][2]")
     re = v[:, :, 0].astype(np.int64)
     im = v[:, :, 1].astype(np.int64)
-    return np.ascontiguousarray((re * re + im * im).astype(np.float32).T)
+    return (re * re + im * im).astype(np.float32)
 
 
 # --------------------------------------------------------------------------

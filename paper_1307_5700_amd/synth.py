@@ -98,6 +98,21 @@ def noise(shape, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape, dtype=np.float32)
 
 
+def voltages(nchans: int, nsamps: int, seed: int, sigma: float = 2000.0, clip_frac: float = 1e-4) -> np.ndarray:
+    """Beamformed 16-bit complex voltages [nchans][nsamps][2] (re, im) in
+    channel/time order: a complex Gaussian of standard deviation sigma per
+    component, rounded and saturated to int16, with a fraction clip_frac of
+    samples forced to the int16 extremes (saturated RFI)."""
+    rng = np.random.default_rng(seed)
+    v = np.clip(np.rint(rng.standard_normal((nchans, nsamps, 2), dtype=np.float32) * sigma), -32768, 32767)
+    v = v.astype(np.int16)
+    k = int(clip_frac * nsamps * nchans)
+    if k:
+        c, t = rng.integers(0, nchans, k), rng.integers(0, nsamps, k)
+        v[c, t] = rng.choice(np.array([-32768, 32767], np.int16), size=(k, 2))
+    return v
+
+
 def quantise(v: np.ndarray, dtype: str) -> np.ndarray:
     if dtype == "f32":
         return np.ascontiguousarray(v, dtype=np.float32)

@@ -135,3 +135,27 @@ def test_mulaw_mutants_fail_pins():
     }
     for name, m in mutants.items():
         assert not np.array_equal(m, good.astype(np.float64)), name
+
+
+def test_power_mutants_fail_pins():
+    """Slips in the power step: the imaginary part dropped, re^2 - im^2, the
+    squares rounded to FP32 before the sum, the magnitude instead of the
+    power, and the channel/time axes transposed; each fails the brute-force
+    pin (Python integers, IEEE single rounding) on its inputs."""
+    from test_oracle_power import _f32
+    C, T = 8, 17
+    rng = np.random.default_rng(T * 100 + C)
+    v = rng.integers(-32768, 32768, size=(C, T, 2), dtype=np.int64).astype(np.int16)
+    want = np.array([[_f32(int(v[c, t, 0]) ** 2 + int(v[c, t, 1]) ** 2) for t in range(T)] for c in range(C)],
+                    np.float32)
+    assert np.array_equal(oracle.power_from_voltages(v), want)
+    re, im = v[..., 0].astype(np.int64), v[..., 1].astype(np.int64)
+    mutants = {
+        "no_imag": (re * re).astype(np.float32),
+        "minus": (re * re - im * im).astype(np.float32),
+        "fp32_squares": (re * re).astype(np.float32) + (im * im).astype(np.float32),
+        "magnitude": np.sqrt((re * re + im * im).astype(np.float64)).astype(np.float32),
+        "transposed": np.ascontiguousarray((re * re + im * im).astype(np.float32).T),
+    }
+    for name, m in mutants.items():
+        assert m.shape != want.shape or not np.array_equal(m, want), name
