@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median", "mulaw"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median", "mulaw",
+                                                             "power"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -61,6 +62,10 @@ def parse():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
                          "WRITE_SIZE) into the workload's profiles/*_traffic.txt and exit")
+    ap.add_argument("--stats-from", nargs="+", metavar="CSV",
+                    help="turn a rocprofv3 --kernel-trace --stats run of this workload (kernel_stats.csv, "
+                         "kernel_trace.csv, optionally the JSON line the profiled run printed) into the "
+                         "workload's profiles/*_kernel_stats.txt and exit")
     return ap.parse_args()
 
 
@@ -76,6 +81,8 @@ TRAFFIC = {
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
     "mulaw": ("mulaw_encode_kernel", "mulaw_traffic.txt", ("mulaw.hip", "internal.h"),
               "one mulaw_encode_kernel launch, mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
+    "power": ("power_kernel", "power_traffic.txt", ("power.hip", "internal.h"),
+              "one power_kernel launch, power workload (1024 ch x 65536 int16 complex voltage samples)"),
 }
 
 
@@ -124,6 +131,70 @@ def traffic_summary(fetch_csv: str, write_csv: str, workload: str) -> None:
     print(open(path).read())
 
 
+STATS = {
+    "paper": ("paper_beam_f32_rfi_kernel_stats.txt",
+              "kernel trace of the default workload (1024 ch x 65536 f32 samples x 640 DMs, RFI on)"),
+    "median": ("median_640dm_59434samp_kernel_stats.txt",
+               "kernel trace of the median workload (640 DMs x 59434 f32 outputs; h = 2, 1, 4, 8, 16)"),
+    "mulaw": ("mulaw_1024ch_65536samp_kernel_stats.txt",
+              "kernel trace of the mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
+    "power": ("power_1024ch_65536samp_kernel_stats.txt",
+              "kernel trace of the power workload (1024 ch x 65536 int16 complex voltage samples)"),
+}
+
+
+def _event_kernel_ms(workload: str, res: dict):
+    """The bench's own HIP-event time per launch of the workload's kernel."""
+    if workload == "paper":
+        return res["stages_ms"]["dedisp"]
+    if workload == "median":
+        return res["half_widths"]["2"]["kernel_ms"]
+    if workload == "mulaw":
+        return res["encode_kernel_ms"]
+    if workload == "power":
+        return res["kernel_ms"]
+    return None
+
+
+def stats_summary(paths, workload: str, steps: int) -> None:
+    """Top kernels of a profiled bench run, the per-dispatch durations of
+    the workload's roofline kernel and, given the run's JSON line, the
+    bench's HIP-event time for the same launches."""
+    import csv
+    kname = TRAFFIC[workload][0]
+    fname, desc = STATS[workload]
+    rows = list(csv.DictReader(open(paths[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    wl = "" if workload == "paper" else f" --workload {workload}"
+    out = [f"# {desc}",
+           f"# command: cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+           f"-d OUT -o bench -- python3 REPO/bench.py{wl} --steps {steps} --warmup 2 --no-cpu-baseline > OUT/bench.json",
+           f"# then: python bench.py{wl} --steps {steps} --stats-from OUT/bench_kernel_stats.csv "
+           "OUT/bench_kernel_trace.csv OUT/bench.json",
+           f"kernel_source_hash={_kernel_hash(TRAFFIC[workload][2])}", "",
+           f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'share':>6s}"]
+    for r in rows[:14]:
+        name = r["Name"] if len(r["Name"]) <= 70 else r["Name"][:67] + "..."
+        out.append(f"{name:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                   f"{100 * float(r['TotalDurationNs']) / tot:5.1f}%")
+    tr = [r for r in csv.DictReader(open(paths[1])) if kname in r["Kernel_Name"]]
+    tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr]
+    out += ["", f"{kname} per dispatch (us, in order): " + " ".join(f"{x:.1f}" for x in d),
+            f"{kname} mean of the last {steps} dispatches (the timed steps): {np.mean(d[-steps:]):.1f} us; "
+            f"grid {tr[-1]['Grid_Size_X']}, workgroup {tr[-1]['Workgroup_Size_X']}"]
+    if len(paths) > 2:
+        lines = [l for l in open(paths[2]) if l.startswith("{")]
+        ev = _event_kernel_ms(workload, json.loads(lines[-1]))
+        out.append(f"{kname} by the bench's HIP events on its stream, same run: {ev * 1e3:.1f} us per launch")
+    path = os.path.join(ROOT, "profiles", fname)
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(open(path).read())
+
+
 def _traffic(workload: str):
     """HBM bytes per launch from the committed PMC summary, if it was taken
     on the kernel's current source (None otherwise)."""
@@ -168,6 +239,9 @@ def main():
     if args.traffic_from:
         traffic_summary(*args.traffic_from, args.workload)
         return
+    if args.stats_from:
+        stats_summary(args.stats_from, args.workload, args.steps)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (sharding by beam, "
               "DM range or time span is not implemented)", file=sys.stderr)
@@ -176,7 +250,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "paper":
         res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
-               "median": bench_median, "mulaw": bench_mulaw}[args.workload](args)
+               "median": bench_median, "mulaw": bench_mulaw, "power": bench_power}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     from paper_1307_5700_amd import api as A
@@ -554,6 +628,58 @@ def bench_mulaw(args):
                                  "sample": f"encode of {rows} channels x {T} samples, {reps} passes in "
                                            f"{cpu_s * reps:.1f} s (numpy, one thread)"}
     res = _line(C * T / dt, dt, args, "f32", cfg, extra)
+    res["metric"] = res["unit"] = "samples/s"
+    return res
+
+
+def bench_power(args):
+    """Power calculation (Sec. 2.2) on the paper-shaped chunk: 1024 channels
+    x 65536 samples of 16-bit complex voltages in channel/time order -> the
+    FP32 filterbank plane [1024][65536] the rest of the path reads.  One
+    step = one launch; HIP events on the stream time it."""
+    import torch
+    import oracle
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    C, T = 1024, 65536
+    vh = synth.voltages(C, T, seed=11)
+    v = torch.from_numpy(vh).cuda()
+    out = A.power_from_voltages(v)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        A.power_from_voltages(v, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        A.power_from_voltages(v, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    k_ms = e0.elapsed_time(e1) / args.steps
+    if args.calib_copy:
+        _calib_copy()
+    nbytes = C * T * (4 + 4)               # read 4 bytes of voltage, write 4 bytes of power per sample
+    rows = 128                             # CPU baseline sample: channel rows
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.power_from_voltages(vh[:rows])
+        reps += 1
+        if time.perf_counter() - t0 > min(args.cpu_seconds, 10.0):
+            break
+    cpu_s = (time.perf_counter() - t0) / reps
+    cfg = {"workload": "power_1024ch_65536samp_int16", "nchans": C, "nsamps": T, "parallelism": "none"}
+    gbs = nbytes / (k_ms * 1e-3) / 1e9
+    extra = {"roofline": {"bound": "hbm", "kernel": "power_kernel", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": _traffic("power")},
+             "kernel_ms": k_ms}
+    if not args.no_cpu_baseline:
+        extra["cpu_baseline"] = {"value": rows * T / cpu_s, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"{rows} channels x {T} samples, {reps} passes in {cpu_s * reps:.1f} s "
+                                           f"(numpy, one thread)"}
+    res = _line(C * T / dt, dt, args, "int32", cfg, extra)
     res["metric"] = res["unit"] = "samples/s"
     return res
 

@@ -255,6 +255,19 @@ mb_status dedisp_normalise(const mb_plan* plan, const float* d_out, int64_t nout
 mb_status median_filter(const float* d_in, int64_t ld_in, float* d_out, int64_t ld_out,
                         int32_t nrows, int64_t ncols, int32_t half_width, void* stream);
 
+/* Channelised power of beamformed voltages (Sec. 2.2): d_in holds a
+ * beam's 16-bit complex samples in channel/time order (Sec. 2.1), channel
+ * row c at d_in + 2*c*ld_in, each sample a (re, im) pair of int16 (ld_in >=
+ * nsamps, in complex samples); d_out [nchans][ld_out] FP32 (ld_out >=
+ * nsamps) receives re^2 + im^2, exact in integers and rounded once to FP32:
+ * the filterbank layout rfi_threshold and dedisp_execute read.  Device
+ * planes owned by the caller; the output must not overlap the input.
+ * Asynchronous on stream.  Errors: MB_EINVAL for negative sizes, NULL or
+ * overlapping planes, a leading dimension below the row length, or a plane
+ * beyond one launch. */
+mb_status power_from_voltages(const int16_t* d_in, int64_t ld_in, int32_t nchans, int64_t nsamps,
+                              float* d_out, int64_t ld_out, void* stream);
+
 /* mu-law codec of the data writer (Sec. 2.4, Eq. 5) for FP32 power planes.
  * mulaw_encode: for every row of d_in [nrows][ld_in] (ncols samples, ld_in
  * >= ncols) X = the row's largest |x| goes to d_xmax[row], and every sample

@@ -80,6 +80,7 @@ _SIGS = {
                         ctypes.POINTER(ExecInfo), c_vp], c_i32),
     "dedisp_normalise": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_vp], c_i32),
     "median_filter": ([c_vp, c_i64, c_vp, c_i64, c_i32, c_i64, c_i32, c_vp], c_i32),
+    "power_from_voltages": ([c_vp, c_i64, c_i32, c_i64, c_vp, c_i64, c_vp], c_i32),
     "mulaw_encode": ([c_vp, c_i64, c_i32, c_i64, ctypes.c_float, c_vp, c_i64, c_vp, c_vp], c_i32),
     "mulaw_decode": ([c_vp, c_i64, c_vp, c_i32, c_i64, ctypes.c_float, c_vp, c_i64, c_vp], c_i32),
     "dedisp_beam_create": ([c_vp, ctypes.POINTER(c_vp)], c_i32),

@@ -255,6 +255,23 @@ def median_filter(plane: torch.Tensor, ncols: int, half_width: int, out: torch.T
     return out
 
 
+def power_from_voltages(v: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Channelised power (Sec. 2.2) of 16-bit complex voltages v, an int16
+    device tensor [C][T][2] (re, im) in channel/time order (dim 1 may be a
+    view of wider rows): returns FP32 [C][ld] with ld = T rounded up to 4,
+    power in the first T columns."""
+    if v.dtype != torch.int16 or v.dim() != 3 or v.shape[2] != 2 or v.stride(2) != 1 or v.stride(1) != 2:
+        raise ValueError("v must be an int16 [C][T][2] tensor with packed (re, im) pairs")
+    C, T = int(v.shape[0]), int(v.shape[1])
+    if out is None:
+        out = torch.empty((C, max((T + 3) // 4 * 4, 4)), dtype=torch.float32, device=v.device)
+    if out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1 or out.shape[0] != C:
+        raise ValueError("out must be a row-major float32 [C][ld] tensor")
+    L.check(L.lib().power_from_voltages(_ptr(v), v.stride(0) // 2 if C > 1 else T, C, T, _ptr(out),
+                                        out.stride(0), _stream_ptr(stream)), "power_from_voltages")
+    return out
+
+
 def mulaw_encode(x: torch.Tensor, ncols: int, mu: float = 255.0, codes: torch.Tensor | None = None,
                  xmax: torch.Tensor | None = None, stream=None):
     """mu-law codes (Sec. 2.4, Eq. 5) of the first `ncols` samples of every

@@ -30,6 +30,7 @@ SOURCES = {
     "detect.hip": [],
     "median.hip": [],
     "mulaw.hip": [],
+    "power.hip": [],
     "mbtp.cpp": ["-x", "hip", "-ffp-contract=off"],
 }
 

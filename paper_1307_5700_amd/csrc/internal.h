@@ -8,6 +8,11 @@
 
 namespace mbtp {
 
+// Four FP32 lanes as a clang vector: the operand type of 16-byte
+// __builtin_nontemporal_store, which streaming writers use for planes that
+// are written once and read by the next stage.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Samples of one wave-span of the statistics pass: a wave covers 256
 // consecutive samples of one channel, 4 per lane.
 constexpr int kSpan = 256;
@@ -200,6 +205,11 @@ int64_t median_tile();
 int64_t median_max_workgroups();
 hipError_t launch_median(const float* in, int64_t ld_in, float* out, int64_t ld_out, int32_t nrows,
                          int64_t ncols, int32_t half_width, hipStream_t s);
+
+// Power of beamformed voltages (power.hip): [C][ld_in] complex int16 ->
+// [C][ld_out] FP32.
+hipError_t launch_power(const int16_t* in, int64_t ld_in, int32_t C, int64_t T, float* out, int64_t ld_out,
+                        hipStream_t s);
 
 // mu-law codec of the data writer (mulaw.hip).
 hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,

@@ -698,6 +698,22 @@ static mb_status mulaw_check(int32_t nrows, int64_t ncols, float mu) {
   return MB_OK;
 }
 
+mb_status power_from_voltages(const int16_t* d_in, int64_t ld_in, int32_t nchans, int64_t nsamps, float* d_out,
+                              int64_t ld_out, void* stream) {
+  if (nchans < 0 || nsamps < 0) return fail(MB_EINVAL, "nchans and nsamps must be >= 0");
+  if (nchans == 0 || nsamps == 0) return ok();
+  if (nsamps > kMaxSamps) return fail(MB_EINVAL, "nsamps %lld exceeds %lld", (long long)nsamps, (long long)kMaxSamps);
+  if ((nsamps + 4095) / 4096 > 2147483647 / nchans) return fail(MB_EINVAL, "plane too large for one launch");
+  uintptr_t i0, i1, o0, o1;
+  mb_status st;
+  // input rows of ld_in complex samples, 4 bytes each
+  if ((st = plane_span(d_in, ld_in, nchans, nsamps, 4, "input", i0, i1)) != MB_OK) return st;
+  if ((st = plane_span(d_out, ld_out, nchans, nsamps, 4, "output", o0, o1)) != MB_OK) return st;
+  if (i0 < o1 && o0 < i1) return fail(MB_EINVAL, "output must not overlap the input");
+  HIP_TRY(launch_power(d_in, ld_in, nchans, nsamps, d_out, ld_out, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 mb_status mulaw_encode(const float* d_in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
                        uint8_t* d_codes, int64_t ld_codes, float* d_xmax, void* stream) {
   mb_status st = mulaw_check(nrows, ncols, mu);

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kMedThreads) void median_kernel(const float* __rest
   const int64_t m = t0 + 4 * threadIdx.x;
   float* o = out + row * ld_out;
   if (full) {
-    reinterpret_cast<float4*>(o + t0)[threadIdx.x] = make_float4(res[0], res[1], res[2], res[3]);
+    // nontemporal: the filtered plane is written once and read by the next stage
+    __builtin_nontemporal_store(f32x4{res[0], res[1], res[2], res[3]}, reinterpret_cast<f32x4*>(o + m));
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)

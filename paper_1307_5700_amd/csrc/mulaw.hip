@@ -25,6 +25,12 @@ namespace {
 constexpr double kLevels = 255.0;
 constexpr int kDecodeTile = 8192;     // samples per decode workgroup (one 256-entry table each)
 
+// Rows of at most kHeld * 4096 samples (16-byte aligned) are held in
+// registers between the max pass and the code pass, so the plane is read
+// from HBM once; longer or unaligned rows are read twice.
+constexpr int kHeld = 16;          // float4 per thread
+
+template <bool HELD>
 __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restrict__ in, int64_t ld_in,
                                                             int64_t ncols, double mu, double l1mu,
                                                             uint8_t* __restrict__ codes, int64_t ld_codes,
@@ -37,9 +43,27 @@ __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restr
   const int tid = threadIdx.x;
   const int64_t n4 = vin ? ncols / 4 : 0;
   float m = 0.0f;
-  for (int64_t i = tid; i < n4; i += 1024) {
-    const float4 v = reinterpret_cast<const float4*>(r)[i];
-    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  float4 held[HELD ? kHeld : 1];
+  if (HELD) {
+#pragma unroll
+    for (int k = 0; k < kHeld; ++k) {
+      const int64_t i = tid + 1024 * k;
+      held[k] = i < n4 ? reinterpret_cast<const float4*>(r)[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  // expm1 of level boundary tid - 1/2, independent of the row: formed while
+  // the row's loads are in flight
+  double e = 0.0;
+  if (tid >= 1 && tid <= 255) e = expm1(__dmul_rn(((double)tid - 0.5) / kLevels, l1mu));
+  if (HELD) {
+#pragma unroll
+    for (int k = 0; k < kHeld; ++k)
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(held[k].x), fabsf(held[k].y)), fmaxf(fabsf(held[k].z), fabsf(held[k].w))));
+  } else {
+    for (int64_t i = tid; i < n4; i += 1024) {
+      const float4 v = reinterpret_cast<const float4*>(r)[i];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
   }
   for (int64_t i = 4 * n4 + tid; i < ncols; i += 1024) m = fmaxf(m, fabsf(r[i]));
 #pragma unroll
@@ -51,8 +75,7 @@ __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restr
   for (int k = 0; k < 16; ++k) X = fmaxf(X, sh[k]);
   if (tid == 0) xmax[row] = X;
   if (tid >= 1 && tid <= 255) {
-    const double b = __dmul_rn(__ddiv_rn((double)X, mu),
-                               expm1(__dmul_rn(((double)tid - 0.5) / kLevels, l1mu)));
+    const double b = __dmul_rn(__ddiv_rn((double)X, mu), e);
     float f = (float)b;
     if ((double)f < b) f = nextafterf(f, INFINITY);
     bound[tid] = f;
@@ -76,10 +99,28 @@ __global__ __launch_bounds__(1024) void mulaw_encode_kernel(const float* __restr
     q -= (xc < bound[q]) ? 1 : 0;
     return (uint32_t)q;
   };
+  if (HELD) {
+#pragma unroll
+    for (int k = 0; k < kHeld; ++k) {
+      const int64_t i = tid + 1024 * k;
+      if (i >= n4) break;
+      const float4 v = held[k];
+      const uint32_t w = code(v.x) | (code(v.y) << 8) | (code(v.z) << 16) | (code(v.w) << 24);
+      if (vout) {
+        __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(c) + i);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[4 * i + j] = (uint8_t)(w >> (8 * j));
+      }
+    }
+    for (int64_t i = 4 * n4 + tid; i < ncols; i += 1024) c[i] = (uint8_t)code(r[i]);
+    return;
+  }
   const int64_t q4 = (vin && vout) ? ncols / 4 : 0;
   for (int64_t i = tid; i < q4; i += 1024) {
     const float4 v = reinterpret_cast<const float4*>(r)[i];
-    reinterpret_cast<uint32_t*>(c)[i] = code(v.x) | (code(v.y) << 8) | (code(v.z) << 16) | (code(v.w) << 24);
+    __builtin_nontemporal_store(code(v.x) | (code(v.y) << 8) | (code(v.z) << 16) | (code(v.w) << 24),
+                                reinterpret_cast<uint32_t*>(c) + i);
   }
   for (int64_t i = 4 * q4 + tid; i < ncols; i += 1024) c[i] = (uint8_t)code(r[i]);
 }
@@ -101,8 +142,8 @@ __global__ __launch_bounds__(256) void mulaw_decode_kernel(const uint8_t* __rest
     const int64_t m = base + 1024 * j + 4 * threadIdx.x;
     if (vec && m + 3 < ncols) {
       const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m);
-      *reinterpret_cast<float4*>(o + m) = make_float4(lut[w & 0xffu], lut[(w >> 8) & 0xffu],
-                                                      lut[(w >> 16) & 0xffu], lut[w >> 24]);
+      __builtin_nontemporal_store(f32x4{lut[w & 0xffu], lut[(w >> 8) & 0xffu], lut[(w >> 16) & 0xffu], lut[w >> 24]},
+                                  reinterpret_cast<f32x4*>(o + m));
     } else {
       for (int q = 0; q < 4; ++q)
         if (m + q < ncols) o[m + q] = lut[c[m + q]];
@@ -116,8 +157,12 @@ hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, in
                                uint8_t* codes, int64_t ld_codes, float* xmax, hipStream_t s) {
   const int vin = (reinterpret_cast<uintptr_t>(in) % 16 == 0 && ld_in % 4 == 0) ? 1 : 0;
   const int vout = (reinterpret_cast<uintptr_t>(codes) % 4 == 0 && ld_codes % 4 == 0) ? 1 : 0;
-  hipLaunchKernelGGL(mulaw_encode_kernel, dim3((unsigned)nrows), dim3(1024), 0, s, in, ld_in, ncols,
-                     (double)mu, log1p((double)mu), codes, ld_codes, xmax, vin, vout);
+  if (vin && ncols <= (int64_t)kHeld * 4096)
+    hipLaunchKernelGGL(mulaw_encode_kernel<true>, dim3((unsigned)nrows), dim3(1024), 0, s, in, ld_in, ncols,
+                       (double)mu, log1p((double)mu), codes, ld_codes, xmax, vin, vout);
+  else
+    hipLaunchKernelGGL(mulaw_encode_kernel<false>, dim3((unsigned)nrows), dim3(1024), 0, s, in, ld_in, ncols,
+                       (double)mu, log1p((double)mu), codes, ld_codes, xmax, vin, vout);
   return hipGetLastError();
 }
 

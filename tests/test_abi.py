@@ -127,3 +127,17 @@ def test_mulaw_rejects_bad_arguments():
     assert lib.mulaw_decode(b, 100, x, -1, 100, 255.0, a, 100, None) == L.MB_EINVAL
     assert lib.mulaw_encode(None, 0, 0, 100, 255.0, None, 0, None, None) == L.MB_OK        # no rows
     assert lib.mulaw_decode(None, 0, None, 4, 0, 255.0, None, 0, None) == L.MB_OK
+
+
+def test_power_rejects_bad_arguments():
+    L = _lib()
+    lib = L.lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 34)
+    assert lib.power_from_voltages(a, 99, 64, 100, b, 100, None) == L.MB_EINVAL              # ld_in < nsamps
+    assert lib.power_from_voltages(a, 100, 64, 100, b, 99, None) == L.MB_EINVAL              # ld_out < nsamps
+    assert lib.power_from_voltages(None, 100, 64, 100, b, 100, None) == L.MB_EINVAL
+    assert lib.power_from_voltages(a, 100, 64, 100, None, 100, None) == L.MB_EINVAL
+    assert lib.power_from_voltages(a, 100, -1, 100, b, 100, None) == L.MB_EINVAL
+    assert lib.power_from_voltages(a, 100, 64, 100, ctypes.c_void_p((1 << 20) + 64), 100, None) == L.MB_EINVAL
+    assert lib.power_from_voltages(None, 0, 0, 100, None, 0, None) == L.MB_OK                # nothing to do
+    assert lib.power_from_voltages(None, 0, 64, 0, None, 0, None) == L.MB_OK
