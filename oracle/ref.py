@@ -482,6 +482,55 @@ def mulaw_decode(codes: np.ndarray, X: np.ndarray, mu: float = 255.0) -> np.ndar
     return (Xd / float(mu) * np.expm1(q / MULAW_LEVELS * math.log1p(float(mu)))).astype(np.float32)
 
 
+MULAW_CPLX_LEVELS = 7   # magnitude levels of a 4-bit sign-magnitude component code
+
+
+def mulaw_cplx_levels(v: np.ndarray, mu: float):
+    """Eq. (5) for complex voltages [rows][T][2] int16, as a fraction of the
+    magnitude code range: w = 7 * log(1 + mu*|x|/X) / log(1 + mu) per
+    component, X the row's largest |component| over both parts.  Returns
+    (w in FP64 [rows][T][2], X per row as int64).
+
+    Reading: a channel's complex series is one series of Eq. (5), so its
+    real and imaginary parts share X; sign[x] takes the code's top bit and
+    the remaining 3 bits the magnitude level; a row of zeros has X = 0 and
+    w = 0."""
+    v = np.asarray(v)
+    if v.dtype != np.int16 or v.ndim != 3 or v.shape[2] != 2:
+        raise ValueError("voltages must be int16 [rows][T][2]")
+    a = np.abs(v.astype(np.int64))
+    X = a.reshape(a.shape[0], -1).max(axis=1) if a.shape[1] else np.zeros(a.shape[0], np.int64)
+    Xd = X.astype(np.float64)[:, None, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(Xd > 0, MULAW_CPLX_LEVELS * np.log1p(float(mu) * a / Xd) / math.log1p(float(mu)), 0.0)
+    return w, X
+
+
+def mulaw_encode_complex(v: np.ndarray, mu: float = 255.0):
+    """4+4-bit mu-law codes of 16-bit complex voltages (Sec. 2.4): one byte
+    per complex sample, the real part's code in the low nibble and the
+    imaginary part's in the high nibble.  A component's code is
+    8*[x < 0] + floor(w + 0.5), the nearest magnitude level taken in FP64
+    with the sign in bit 3 (zero is coded +0).  Returns (codes u8 [rows][T],
+    X per row)."""
+    w, X = mulaw_cplx_levels(v, mu)
+    m = np.floor(w + 0.5).astype(np.int64)
+    nib = m + 8 * (np.asarray(v) < 0)
+    return (nib[..., 0] | (nib[..., 1] << 4)).astype(np.uint8), X
+
+
+def mulaw_decode_complex(codes: np.ndarray, X: np.ndarray, mu: float = 255.0) -> np.ndarray:
+    """Inverse of Eq. (5) at the 4-bit code levels: each nibble gives
+    sign * X/mu * ((1+mu)^(m/7) - 1), rounded to FP32; returns [rows][T][2]
+    (re, im)."""
+    c = np.asarray(codes, dtype=np.int64)
+    nib = np.stack([c & 15, c >> 4], axis=-1)
+    m = (nib & 7).astype(np.float64)
+    sgn = np.where(nib >= 8, -1.0, 1.0)
+    Xd = np.asarray(X, dtype=np.float64)[:, None, None]
+    return (sgn * (Xd / float(mu) * np.expm1(m / MULAW_CPLX_LEVELS * math.log1p(float(mu))))).astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # Event detection: n-sigma threshold, Sec. 2.3
 # --------------------------------------------------------------------------

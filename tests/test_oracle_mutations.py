@@ -159,3 +159,36 @@ def test_power_mutants_fail_pins():
     }
     for name, m in mutants.items():
         assert m.shape != want.shape or not np.array_equal(m, want), name
+
+
+def test_mulaw_complex_mutants_fail_pins():
+    """Slips in the 4+4-bit codec: the sign dropped, X from the real part
+    only, the nibbles swapped, 8 magnitude levels, floor instead of
+    nearest; each changes the codes of the pinned nibble-order row."""
+    X, mu = 20000, 255.0
+    k3 = int(round(X / mu * math.expm1(3 / 7.0 * math.log1p(mu))))
+    k5 = int(round(X / mu * math.expm1(5 / 7.0 * math.log1p(mu))))
+    # row 0: the nibble-order row; row 1: the largest magnitude only in the imaginary part
+    v = np.array([[(X, 0), (0, X), (-X, 0), (0, -X), (k3, 0), (k3, X), (-k3, -k3)],
+                  [(k3, X), (-k3, 0), (k5, 0), (0, 0), (0, 0), (0, 0), (0, 0)]], np.int16)
+    good, _ = oracle.mulaw_encode_complex(v, mu)
+    assert list(map(int, good[0, :5])) == [0x07, 0x70, 0x0F, 0xF0, 0x03]
+    assert list(map(int, good[1, :3])) == [0x73, 0x0B, 0x05]
+    a = np.abs(v.astype(np.int64)).astype(np.float64)
+    L = np.log1p(mu * a / X) / math.log1p(mu)
+
+    def pack(nib):
+        return (nib[..., 0] | (nib[..., 1] << 4)).astype(np.uint8)
+
+    neg = (v < 0).astype(np.int64)
+    Xre = np.max(np.abs(v[..., 0].astype(np.int64)), axis=1)[:, None, None].astype(np.float64)
+    mutants = {
+        "no_sign": pack(np.floor(7 * L + 0.5).astype(np.int64)),
+        "x_from_real": pack(np.floor(7 * np.log1p(mu * a / Xre) / math.log1p(mu) + 0.5).astype(np.int64)
+                            .clip(0, 7) + 8 * neg),
+        "nibbles_swapped": pack(np.floor(7 * L + 0.5).astype(np.int64)[..., ::-1] + 8 * neg[..., ::-1]),
+        "levels_8": pack(np.floor(8 * L + 0.5).astype(np.int64).clip(0, 7) + 8 * neg),
+        "floor": pack(np.floor(7 * L).astype(np.int64) + 8 * neg),
+    }
+    for name, m in mutants.items():
+        assert not np.array_equal(m, good), name
