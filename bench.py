@@ -603,6 +603,13 @@ def bench_mulaw(args):
 
     dt, k_ms = timed(lambda: A.mulaw_encode(x, T, codes=codes, xmax=xmax))
     ddt, dk_ms = timed(lambda: A.mulaw_decode(codes, xmax, T, out=dec))
+    # the complex format: 4+4-bit codes of the same chunk as 16-bit voltages
+    v = torch.from_numpy(synth.voltages(C, T, seed=11)).cuda()
+    ccodes, cxmax = A.mulaw_encode_complex(v)
+    cdec = A.mulaw_decode_complex(ccodes, cxmax, T)
+    cdt, ck_ms = timed(lambda: A.mulaw_encode_complex(v, codes=ccodes, xmax=cxmax))
+    cddt, cdk_ms = timed(lambda: A.mulaw_decode_complex(ccodes, cxmax, T, out=cdec))
+    del v, cdec
     if args.calib_copy:
         _calib_copy()
     enc_bytes = C * T * (4 + 1)            # read the plane once, write the codes
@@ -622,7 +629,10 @@ def bench_mulaw(args):
                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": enc_bytes / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic("mulaw")},
              "encode_kernel_ms": k_ms,
-             "decode": {"ms_per_step": ddt * 1e3, "kernel_ms": dk_ms, "hbm_gbs": dec_bytes / (dk_ms * 1e-3) / 1e9}}
+             "decode": {"ms_per_step": ddt * 1e3, "kernel_ms": dk_ms, "hbm_gbs": dec_bytes / (dk_ms * 1e-3) / 1e9},
+             "complex_4p4": {"encode_kernel_ms": ck_ms, "encode_hbm_gbs": C * T * 5 / (ck_ms * 1e-3) / 1e9,
+                             "decode_kernel_ms": cdk_ms, "decode_hbm_gbs": C * T * 9 / (cdk_ms * 1e-3) / 1e9,
+                             "input": "1024 ch x 65536 int16 complex samples"}}
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = {"value": rows * T / cpu_s, "unit": "samples/s", "cores": 1, "kind": "oracle",
                                  "sample": f"encode of {rows} channels x {T} samples, {reps} passes in "

@@ -286,6 +286,28 @@ mb_status mulaw_encode(const float* d_in, int64_t ld_in, int32_t nrows, int64_t 
 mb_status mulaw_decode(const uint8_t* d_codes, int64_t ld_codes, const float* d_xmax, int32_t nrows,
                        int64_t ncols, float mu, float* d_out, int64_t ld_out, void* stream);
 
+/* 4+4-bit mu-law codec of 16-bit complex voltages (Sec. 2.4, Eq. 5), the
+ * data writer's format for complex channelised series.  mulaw_encode_complex:
+ * d_in holds nrows channel rows of (re, im) int16 pairs, row r at
+ * d_in + 2*r*ld_in (ld_in >= ncols, both in complex samples).  Each row's
+ * largest |component| X (over both parts) goes to d_xmax[r] (int32, up to
+ * 32768) and each complex sample to one byte of d_codes [nrows][ld_codes]:
+ * the real part's nibble in bits 0-3, the imaginary part's in bits 4-7.  A
+ * nibble is the sign of x in bit 3 and, in bits 0-2, the number of level
+ * boundaries X/mu * expm1((k - 1/2)/7 * log1p(mu)), k = 1..7, formed in
+ * FP64, that |x| reaches (a row of zeros gives X = 0 and codes 0).
+ * mulaw_decode_complex: each nibble becomes sign * X/mu * expm1(m/7 *
+ * log1p(mu)), FP64 rounded to FP32, into d_out, nrows rows of ld_out
+ * (re, im) FP32 pairs (ld_out >= ncols, in complex samples).  mu finite
+ * and > 0.  Device planes owned by the caller; outputs must not overlap
+ * inputs.  Asynchronous on stream.  Errors: MB_EINVAL for negative sizes,
+ * a bad mu, NULL or overlapping planes, a leading dimension below ncols or
+ * a plane beyond one launch (nothing is enqueued). */
+mb_status mulaw_encode_complex(const int16_t* d_in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                               uint8_t* d_codes, int64_t ld_codes, int32_t* d_xmax, void* stream);
+mb_status mulaw_decode_complex(const uint8_t* d_codes, int64_t ld_codes, const int32_t* d_xmax, int32_t nrows,
+                               int64_t ncols, float mu, float* d_out, int64_t ld_out, void* stream);
+
 /* ---- batched launch ------------------------------------------------------ */
 
 /* One beam chunk of a batch: the arguments of one dedisp_execute call. */

@@ -301,6 +301,42 @@ def mulaw_decode(codes: torch.Tensor, xmax: torch.Tensor, ncols: int, mu: float 
     return out
 
 
+def mulaw_encode_complex(v: torch.Tensor, mu: float = 255.0, codes: torch.Tensor | None = None,
+                         xmax: torch.Tensor | None = None, stream=None):
+    """4+4-bit mu-law codes (Sec. 2.4, Eq. 5) of 16-bit complex voltages v,
+    an int16 device tensor [rows][T][2] (re, im) (dim 1 may be a view of
+    wider rows): returns (codes uint8 [rows][ld], one byte per complex
+    sample with the real part in the low nibble, xmax int32 [rows])."""
+    if v.dtype != torch.int16 or v.dim() != 3 or v.shape[2] != 2 or v.stride(2) != 1 or v.stride(1) != 2:
+        raise ValueError("v must be an int16 [rows][T][2] tensor with packed (re, im) pairs")
+    R, T = int(v.shape[0]), int(v.shape[1])
+    if codes is None:
+        codes = torch.empty((R, max((T + 3) // 4 * 4, 4)), dtype=torch.uint8, device=v.device)
+    xmax = torch.empty(R, dtype=torch.int32, device=v.device) if xmax is None else xmax
+    if codes.dtype != torch.uint8 or codes.dim() != 2 or codes.stride(1) != 1 or xmax.dtype != torch.int32:
+        raise ValueError("codes must be a 2-D row-major uint8 tensor and xmax int32")
+    L.check(L.lib().mulaw_encode_complex(_ptr(v), v.stride(0) // 2 if R > 1 else T, R, T, float(mu), _ptr(codes),
+                                         codes.stride(0), _ptr(xmax), _stream_ptr(stream)), "mulaw_encode_complex")
+    return codes, xmax
+
+
+def mulaw_decode_complex(codes: torch.Tensor, xmax: torch.Tensor, ncols: int, mu: float = 255.0,
+                         out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """FP32 (re, im) values [rows][ld][2] of 4+4-bit mu-law codes (the
+    inverse map of Eq. 5 at the 4-bit levels), first `ncols` of each row."""
+    if codes.dtype != torch.uint8 or codes.dim() != 2 or codes.stride(1) != 1:
+        raise ValueError("codes must be a 2-D row-major uint8 tensor")
+    R = int(codes.shape[0])
+    if out is None:
+        out = torch.empty((R, max((int(ncols) + 1) // 2 * 2, 2), 2), dtype=torch.float32, device=codes.device)
+    if out.dtype != torch.float32 or out.dim() != 3 or out.shape[2] != 2 or out.stride(2) != 1 or out.stride(1) != 2:
+        raise ValueError("out must be a float32 [rows][ld][2] tensor with packed (re, im) pairs")
+    L.check(L.lib().mulaw_decode_complex(_ptr(codes), codes.stride(0), _ptr(xmax), R, int(ncols), float(mu),
+                                         _ptr(out), out.stride(0) // 2, _stream_ptr(stream)),
+            "mulaw_decode_complex")
+    return out
+
+
 def num_tilings() -> int:
     """Number of compiled dedispersion tilings (valid tile_hint: 1..n)."""
     n = ctypes.c_int32()

@@ -216,6 +216,12 @@ hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, in
                                uint8_t* codes, int64_t ld_codes, float* xmax, hipStream_t s);
 hipError_t launch_mulaw_decode(const uint8_t* codes, int64_t ld_codes, const float* xmax, int32_t nrows,
                                int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s);
+// 4+4-bit codec of 16-bit complex voltages (mulaw.hip); ld_in, ncols and
+// ld_out count complex samples.
+hipError_t launch_mulaw_encode_complex(const int16_t* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                                       uint8_t* codes, int64_t ld_codes, int32_t* xmax, hipStream_t s);
+hipError_t launch_mulaw_decode_complex(const uint8_t* codes, int64_t ld_codes, const int32_t* xmax, int32_t nrows,
+                                       int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s);
 
 hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
                          const NormDev* norm, int64_t sample0, double nsigma,

@@ -746,6 +746,38 @@ mb_status mulaw_decode(const uint8_t* d_codes, int64_t ld_codes, const float* d_
   return ok();
 }
 
+mb_status mulaw_encode_complex(const int16_t* d_in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                               uint8_t* d_codes, int64_t ld_codes, int32_t* d_xmax, void* stream) {
+  mb_status st = mulaw_check(nrows, ncols, mu);
+  if (st != MB_OK) return st;
+  if (nrows == 0) return ok();
+  if (!d_xmax) return fail(MB_EINVAL, "xmax must not be NULL");
+  uintptr_t i0 = 0, i1 = 0, c0 = 0, c1 = 0;
+  if (ncols > 0) {
+    if ((st = plane_span(d_in, ld_in, nrows, ncols, 4, "input", i0, i1)) != MB_OK) return st;
+    if ((st = plane_span(d_codes, ld_codes, nrows, ncols, 1, "codes", c0, c1)) != MB_OK) return st;
+    if (i0 < c1 && c0 < i1) return fail(MB_EINVAL, "codes must not overlap the input");
+  }
+  HIP_TRY(launch_mulaw_encode_complex(d_in, ld_in, nrows, ncols, mu, d_codes, ld_codes, d_xmax,
+                                      static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mb_status mulaw_decode_complex(const uint8_t* d_codes, int64_t ld_codes, const int32_t* d_xmax, int32_t nrows,
+                               int64_t ncols, float mu, float* d_out, int64_t ld_out, void* stream) {
+  mb_status st = mulaw_check(nrows, ncols, mu);
+  if (st != MB_OK) return st;
+  if (nrows == 0 || ncols == 0) return ok();
+  if (!d_xmax) return fail(MB_EINVAL, "xmax must not be NULL");
+  uintptr_t c0, c1, o0, o1;
+  if ((st = plane_span(d_codes, ld_codes, nrows, ncols, 1, "codes", c0, c1)) != MB_OK) return st;
+  if ((st = plane_span(d_out, ld_out, nrows, ncols, 8, "output", o0, o1)) != MB_OK) return st;
+  if (c0 < o1 && o0 < c1) return fail(MB_EINVAL, "output must not overlap the codes");
+  HIP_TRY(launch_mulaw_decode_complex(d_codes, ld_codes, d_xmax, nrows, ncols, mu, d_out, ld_out,
+                                      static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MB_EINVAL, "plan and bytes must not be NULL");
   *bytes = detect_work_bytes(plan->desc.ndms);

@@ -151,7 +151,142 @@ __global__ __launch_bounds__(256) void mulaw_decode_kernel(const uint8_t* __rest
   }
 }
 
+// ---- 4+4-bit codec of 16-bit complex voltages -------------------------------
+// Encode: one 1024-thread workgroup per channel row of (re, im) int16 pairs.
+// X is the row's largest |component| (an integer up to 32768).  A
+// component's magnitude level is the number of boundaries
+// b_k = X/mu * expm1((k - 1/2)/7 * log1p(mu)), k = 1..7, that |x| reaches;
+// |x| is an integer, so that is the number of integer thresholds ceil(b_k)
+// (formed in FP64) it reaches.  The nibble is the level with the sign of x
+// in bit 3; the real part's nibble is the byte's low half.
+constexpr int kCplxLevels = 7;
+
+__device__ inline uint32_t cplx_nibble(int32_t x, const int32_t (&thr)[kCplxLevels]) {
+  const int32_t a = x < 0 ? -x : x;
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < kCplxLevels; ++k) m += a >= thr[k] ? 1u : 0u;
+  return m | (x < 0 ? 8u : 0u);
+}
+
+__device__ inline uint32_t cplx_byte(uint32_t w, const int32_t (&thr)[kCplxLevels]) {
+  return cplx_nibble((int16_t)(w & 0xffffu), thr) | (cplx_nibble((int16_t)(w >> 16), thr) << 4);
+}
+
+__device__ inline int32_t cplx_absmax(uint32_t w) {
+  const int32_t re = (int16_t)(w & 0xffffu), im = (int16_t)(w >> 16);
+  return max(re < 0 ? -re : re, im < 0 ? -im : im);
+}
+
+__global__ __launch_bounds__(1024) void mulaw_encode_complex_kernel(const uint32_t* __restrict__ in, int64_t ld_in,
+                                                                    int64_t ncols, double mu, double l1mu,
+                                                                    uint8_t* __restrict__ codes, int64_t ld_codes,
+                                                                    int32_t* __restrict__ xmax, int vin, int vout) {
+  __shared__ int32_t sh[16];
+  __shared__ int32_t thr_s[kCplxLevels];
+  const int64_t row = blockIdx.x;
+  const uint32_t* r = in + row * ld_in;
+  uint8_t* c = codes + row * ld_codes;
+  const int tid = threadIdx.x;
+  // boundary k + 1/2 without X, formed while the row is read
+  double e = 0.0;
+  if (tid < kCplxLevels) e = expm1(__dmul_rn(((double)tid + 0.5) / kCplxLevels, l1mu));
+  const int64_t n4 = vin ? ncols / 4 : 0;
+  int32_t m = 0;
+  for (int64_t i = tid; i < n4; i += 1024) {
+    const uint4 w = reinterpret_cast<const uint4*>(r)[i];
+    m = max(m, max(max(cplx_absmax(w.x), cplx_absmax(w.y)), max(cplx_absmax(w.z), cplx_absmax(w.w))));
+  }
+  for (int64_t i = 4 * n4 + tid; i < ncols; i += 1024) m = max(m, cplx_absmax(r[i]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+  if ((tid & 63) == 0) sh[tid >> 6] = m;
+  __syncthreads();
+  int32_t X = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) X = max(X, sh[k]);
+  if (tid == 0) xmax[row] = X;
+  if (tid < kCplxLevels) thr_s[tid] = (int32_t)ceil(__dmul_rn(__ddiv_rn((double)X, mu), e));
+  __syncthreads();
+  if (X == 0) {
+    // a row of zeros: every code is 0
+    for (int64_t i = tid; i < ncols; i += 1024) c[i] = 0;
+    return;
+  }
+  int32_t thr[kCplxLevels];
+#pragma unroll
+  for (int k = 0; k < kCplxLevels; ++k) thr[k] = thr_s[k];
+  const int64_t q4 = (vin && vout) ? ncols / 4 : 0;
+  for (int64_t i = tid; i < q4; i += 1024) {
+    const uint4 w = reinterpret_cast<const uint4*>(r)[i];
+    __builtin_nontemporal_store(cplx_byte(w.x, thr) | (cplx_byte(w.y, thr) << 8) | (cplx_byte(w.z, thr) << 16) |
+                                    (cplx_byte(w.w, thr) << 24),
+                                reinterpret_cast<uint32_t*>(c) + i);
+  }
+  for (int64_t i = 4 * q4 + tid; i < ncols; i += 1024) c[i] = (uint8_t)cplx_byte(r[i], thr);
+}
+
+// Decode: one 256-thread workgroup per kDecodeTile complex samples of a row;
+// the 16 values of a row's nibbles are formed once in LDS, and each thread
+// turns two codes at a time into 4 FP32 values.
+__global__ __launch_bounds__(256) void mulaw_decode_complex_kernel(const uint8_t* __restrict__ codes,
+                                                                   int64_t ld_codes, const int32_t* __restrict__ xmax,
+                                                                   int64_t ncols, int64_t ntiles, double mu,
+                                                                   double l1mu, float* __restrict__ out,
+                                                                   int64_t ld_out, int vec) {
+  __shared__ float lut[16];
+  const int64_t row = blockIdx.x / ntiles;
+  const int64_t base = (blockIdx.x % ntiles) * kDecodeTile;
+  const uint8_t* c = codes + row * ld_codes;
+  float* o = out + row * 2 * ld_out;
+  if (threadIdx.x < 16) {
+    const int mag = threadIdx.x & 7;
+    const float v =
+        (float)__dmul_rn(__ddiv_rn((double)xmax[row], mu), expm1(__dmul_rn((double)mag / kCplxLevels, l1mu)));
+    lut[threadIdx.x] = threadIdx.x >= 8 ? -v : v;
+  }
+  __syncthreads();
+  // a 1024-code slab is 512 float4 of output: lane-consecutive 16-byte
+  // stores, each of two codes (re, im, re, im)
+#pragma unroll 4
+  for (int j = 0; j < 2 * kDecodeTile / 1024; ++j) {
+    const int64_t m = base + 512 * j + 2 * threadIdx.x;
+    if (vec && m + 1 < ncols) {
+      const uint32_t w = *reinterpret_cast<const uint16_t*>(c + m);
+      __builtin_nontemporal_store(f32x4{lut[w & 15u], lut[(w >> 4) & 15u], lut[(w >> 8) & 15u], lut[w >> 12]},
+                                  reinterpret_cast<f32x4*>(o + 2 * m));
+    } else {
+      for (int q = 0; q < 2; ++q)
+        if (m + q < ncols) {
+          const uint32_t b = c[m + q];
+          o[2 * (m + q)] = lut[b & 15u];
+          o[2 * (m + q) + 1] = lut[b >> 4];
+        }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_mulaw_encode_complex(const int16_t* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
+                                       uint8_t* codes, int64_t ld_codes, int32_t* xmax, hipStream_t s) {
+  const int vin = (reinterpret_cast<uintptr_t>(in) % 16 == 0 && ld_in % 4 == 0) ? 1 : 0;
+  const int vout = (reinterpret_cast<uintptr_t>(codes) % 4 == 0 && ld_codes % 4 == 0) ? 1 : 0;
+  hipLaunchKernelGGL(mulaw_encode_complex_kernel, dim3((unsigned)nrows), dim3(1024), 0, s,
+                     reinterpret_cast<const uint32_t*>(in), ld_in, ncols, (double)mu, log1p((double)mu), codes,
+                     ld_codes, xmax, vin, vout);
+  return hipGetLastError();
+}
+
+hipError_t launch_mulaw_decode_complex(const uint8_t* codes, int64_t ld_codes, const int32_t* xmax, int32_t nrows,
+                                       int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s) {
+  const int64_t ntiles = (ncols + kDecodeTile - 1) / kDecodeTile;
+  const int vec = (reinterpret_cast<uintptr_t>(codes) % 2 == 0 && ld_codes % 2 == 0 &&
+                   reinterpret_cast<uintptr_t>(out) % 16 == 0 && ld_out % 2 == 0) ? 1 : 0;
+  hipLaunchKernelGGL(mulaw_decode_complex_kernel, dim3((unsigned)(ntiles * nrows)), dim3(256), 0, s, codes,
+                     ld_codes, xmax, ncols, ntiles, (double)mu, log1p((double)mu), out, ld_out, vec);
+  return hipGetLastError();
+}
 
 hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,
                                uint8_t* codes, int64_t ld_codes, float* xmax, hipStream_t s) {

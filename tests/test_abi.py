@@ -141,3 +141,19 @@ def test_power_rejects_bad_arguments():
     assert lib.power_from_voltages(a, 100, 64, 100, ctypes.c_void_p((1 << 20) + 64), 100, None) == L.MB_EINVAL
     assert lib.power_from_voltages(None, 0, 0, 100, None, 0, None) == L.MB_OK                # nothing to do
     assert lib.power_from_voltages(None, 0, 64, 0, None, 0, None) == L.MB_OK
+
+
+def test_mulaw_complex_rejects_bad_arguments():
+    L = _lib()
+    lib = L.lib()
+    a, b, x = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 34)
+    assert lib.mulaw_encode_complex(a, 100, 4, 100, 0.0, b, 100, x, None) == L.MB_EINVAL          # mu <= 0
+    assert lib.mulaw_encode_complex(a, 100, 4, 100, 255.0, b, 100, None, None) == L.MB_EINVAL     # no xmax
+    assert lib.mulaw_encode_complex(a, 99, 4, 100, 255.0, b, 100, x, None) == L.MB_EINVAL         # ld < ncols
+    assert lib.mulaw_encode_complex(a, 100, 4, 100, 255.0, ctypes.c_void_p((1 << 20) + 8), 100, x,
+                                    None) == L.MB_EINVAL                                          # overlap
+    assert lib.mulaw_decode_complex(b, 100, x, 4, 100, 255.0, None, 100, None) == L.MB_EINVAL     # NULL output
+    assert lib.mulaw_decode_complex(b, 100, x, 4, 100, 255.0, a, 99, None) == L.MB_EINVAL         # ld_out < ncols
+    assert lib.mulaw_decode_complex(b, 100, x, 4, 100, 255.0, ctypes.c_void_p((1 << 30) - 64), 100,
+                                    None) == L.MB_EINVAL                                          # overlap
+    assert lib.mulaw_encode_complex(None, 0, 0, 100, 255.0, None, 0, None, None) == L.MB_OK        # no rows
