@@ -565,6 +565,82 @@ def detect(z: np.ndarray, nsigma: float, sample0: int = 0,
 
 
 # --------------------------------------------------------------------------
+# Clustering of detections: DBSCAN in (time, DM, SNR), Sec. 2.3
+# --------------------------------------------------------------------------
+
+def cluster_neighbours(sample, dm_index, snr, t_eps: int, dm_eps: int, snr_eps: float):
+    """Eps-neighbourhoods of the detections (Sec. 2.3): q is in N(p) when
+    |sample_q - sample_p| <= t_eps, |dm_q - dm_p| <= dm_eps and
+    |snr_q - snr_p| <= snr_eps, the last difference taken in FP32 (the
+    precision of the stored SNR).  p is in its own neighbourhood.  Returns a
+    list of index arrays, ascending.
+
+    Reading: the distance gives each dimension its own extent (T_t, DM_t,
+    SNR_t) and a point is a neighbour when it lies within all three, i.e.
+    the Chebyshev norm of the per-dimension scaled differences is <= 1."""
+    sample = np.asarray(sample, np.int64)
+    dm = np.asarray(dm_index, np.int64)
+    snr = np.asarray(snr, np.float32)
+    order = np.argsort(sample, kind="stable")
+    ss = sample[order]
+    lo = np.searchsorted(ss, sample - int(t_eps), "left")
+    hi = np.searchsorted(ss, sample + int(t_eps), "right")
+    out = []
+    for p in range(sample.shape[0]):
+        q = order[lo[p]:hi[p]]
+        keep = (np.abs(dm[q] - dm[p]) <= int(dm_eps)) & \
+               (np.abs(snr[q] - snr[p]) <= np.float32(snr_eps))
+        out.append(np.sort(q[keep]))
+    return out
+
+
+def cluster(sample, dm_index, snr, t_eps: int, dm_eps: int, snr_eps: float, min_pts: int):
+    """DBSCAN labels of the detections (Sec. 2.3): -1 for noise, otherwise
+    the cluster number.  Returns (labels int32, number of clusters).
+
+    Readings: |N(p)| >= min_pts (p included) makes p a core point; a
+    cluster is a maximal set of core points joined by chains of core points
+    in each other's neighbourhoods, plus the border points (non-core points
+    in some core point's neighbourhood).  A border point that two clusters
+    reach joins the one holding its lowest-indexed core neighbour (DBSCAN
+    leaves this to the visiting order).  Clusters are numbered 0, 1, ... in
+    order of their lowest-indexed core point.  The paper's FDBSCAN expands
+    from a few representative points of each neighbourhood instead and can
+    lose points or split clusters; this is the exact result it
+    approximates."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    nb = cluster_neighbours(sample, dm_index, snr, t_eps, dm_eps, snr_eps)
+    n = len(nb)
+    core = np.array([q.shape[0] >= int(min_pts) for q in nb], dtype=bool)
+    rows = [np.full(q.shape[0], p) for p, q in enumerate(nb) if core[p]]
+    cols = [q for p, q in enumerate(nb) if core[p]]
+    if rows:
+        r = np.concatenate(rows)
+        c = np.concatenate(cols)
+        keep = core[c]
+        g = coo_matrix((np.ones(int(keep.sum()), np.int8), (r[keep], c[keep])), shape=(n, n))
+        _, comp = connected_components(g, directed=False)
+    else:
+        comp = np.arange(n)
+    # lowest core index of each component, then the component's number
+    first = {}
+    for p in range(n):
+        if core[p] and comp[p] not in first:
+            first[comp[p]] = p
+    rank = {cid: k for k, cid in enumerate(sorted(first, key=lambda c: first[c]))}
+    labels = np.full(n, -1, np.int32)
+    for p in range(n):
+        if core[p]:
+            labels[p] = rank[comp[p]]
+        else:
+            cn = nb[p][core[nb[p]]]
+            if cn.shape[0]:
+                labels[p] = rank[comp[cn[0]]]
+    return labels, len(first)
+
+
+# --------------------------------------------------------------------------
 # Streaming: chunks of one beam processed in turn (Sec. 2.2.1 cleans each
 # iteration's buffer with its own statistics; Sec. 3's shift buffer carries
 # the samples that later outputs still need across iterations)

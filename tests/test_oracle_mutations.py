@@ -192,3 +192,57 @@ def test_mulaw_complex_mutants_fail_pins():
     }
     for name, m in mutants.items():
         assert not np.array_equal(m, good), name
+
+
+def _cluster_mutant(s, d, q, te, de, se, mp, strict=False, no_self=False, border_high=False,
+                    chain_borders=False, ignore_dm=False):
+    n = len(s)
+    nb = []
+    for i in range(n):
+        row = []
+        for j in range(n):
+            dt, dd = abs(int(s[i]) - int(s[j])), abs(int(d[i]) - int(d[j]))
+            dq = abs(float(np.float32(q[i]) - np.float32(q[j])))
+            ok = (dt < te and (ignore_dm or dd < de) and dq < se) if strict else \
+                 (dt <= te and (ignore_dm or dd <= de) and dq <= se)
+            if ok and not (no_self and i == j):
+                row.append(j)
+        nb.append(row)
+    core = [len(x) >= mp for x in nb]
+    lab = [-1] * n
+    k = 0
+    for i in range(n):
+        if core[i] and lab[i] < 0:
+            lab[i] = k
+            stack = [i]
+            while stack:
+                p = stack.pop()
+                for j in nb[p]:
+                    if lab[j] < 0 and (core[j] or chain_borders):
+                        lab[j] = k
+                        if core[j] or chain_borders:
+                            stack.append(j)
+            k += 1
+    for i in range(n):
+        if not core[i] and not chain_borders:
+            cn = [j for j in nb[i] if core[j]]
+            lab[i] = lab[(max if border_high else min)(cn)] if cn else -1
+    return lab, k
+
+
+def test_cluster_mutants_fail_pins():
+    """Slips in the clustering: strict extents, MinPts without the point
+    itself, a border point to its highest-indexed core neighbour, clusters
+    chained through border points, the DM extent ignored; each changes a
+    pinned hand example's labels."""
+    s, d, q = [0, 1, 2, 5, 8, 9, 10], [0] * 7, [7.0] * 7
+    good = [0, 0, 0, 0, 1, 1, 1]
+    assert list(oracle.cluster(s, d, q, 3, 0, 1.0, 4)[0]) == good
+    assert _cluster_mutant(s, d, q, 3, 0, 1.0, 4)[0] == good
+    assert _cluster_mutant(s, d, q, 3, 0, 1.0, 4, strict=True)[0] != good
+    assert _cluster_mutant(s, d, q, 3, 0, 1.0, 4, no_self=True)[0] != good
+    assert _cluster_mutant(s, d, q, 3, 0, 1.0, 4, border_high=True)[0] != good
+    assert _cluster_mutant(s, d, q, 3, 0, 1.0, 4, chain_borders=True)[0] != good
+    s2, d2, q2 = [0, 1, 2, 0, 1, 2], [0, 0, 0, 9, 9, 9], [7.0] * 6
+    assert list(oracle.cluster(s2, d2, q2, 2, 1, 1.0, 3)[0]) == [0, 0, 0, 1, 1, 1]
+    assert _cluster_mutant(s2, d2, q2, 2, 1, 1.0, 3, ignore_dm=True)[0] != [0, 0, 0, 1, 1, 1]
