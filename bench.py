@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median", "mulaw",
-                                                             "power"])
+                                                             "power", "cluster"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -81,6 +81,8 @@ TRAFFIC = {
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
     "mulaw": ("mulaw_encode_kernel", "mulaw_traffic.txt", ("mulaw.hip", "internal.h"),
               "one mulaw_encode_kernel launch, mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
+    "cluster": ("cluster_union_rows_kernel", "cluster_traffic.txt", ("cluster.hip", "internal.h"),
+                "one cluster_union_rows_kernel launch, cluster workload (53858 detections, 640 DMs)"),
     "power": ("power_kernel", "power_traffic.txt", ("power.hip", "internal.h"),
               "one power_kernel launch, power workload (1024 ch x 65536 int16 complex voltage samples)"),
 }
@@ -138,6 +140,8 @@ STATS = {
                "kernel trace of the median workload (640 DMs x 59434 f32 outputs; h = 2, 1, 4, 8, 16)"),
     "mulaw": ("mulaw_1024ch_65536samp_kernel_stats.txt",
               "kernel trace of the mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
+    "cluster": ("cluster_640dm_59434samp_kernel_stats.txt",
+                "kernel trace of the cluster workload (53858 detections over 640 DMs x 59434 samples)"),
     "power": ("power_1024ch_65536samp_kernel_stats.txt",
               "kernel trace of the power workload (1024 ch x 65536 int16 complex voltage samples)"),
 }
@@ -151,7 +155,7 @@ def _event_kernel_ms(workload: str, res: dict):
         return res["half_widths"]["2"]["kernel_ms"]
     if workload == "mulaw":
         return res["encode_kernel_ms"]
-    if workload == "power":
+    if workload in ("power", "cluster"):
         return res["kernel_ms"]
     return None
 
@@ -188,7 +192,8 @@ def stats_summary(paths, workload: str, steps: int) -> None:
     if len(paths) > 2:
         lines = [l for l in open(paths[2]) if l.startswith("{")]
         ev = _event_kernel_ms(workload, json.loads(lines[-1]))
-        out.append(f"{kname} by the bench's HIP events on its stream, same run: {ev * 1e3:.1f} us per launch")
+        what = "the whole clustering (all its launches)" if workload == "cluster" else kname
+        out.append(f"{what} by the bench's HIP events on its stream, same run: {ev * 1e3:.1f} us per step")
     path = os.path.join(ROOT, "profiles", fname)
     with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")
@@ -250,7 +255,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "paper":
         res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
-               "median": bench_median, "mulaw": bench_mulaw, "power": bench_power}[args.workload](args)
+               "median": bench_median, "mulaw": bench_mulaw, "power": bench_power,
+               "cluster": bench_cluster}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     from paper_1307_5700_amd import api as A
@@ -691,6 +697,69 @@ def bench_power(args):
                                            f"(numpy, one thread)"}
     res = _line(C * T / dt, dt, args, "int32", cfg, extra)
     res["metric"] = res["unit"] = "samples/s"
+    return res
+
+
+def bench_cluster(args):
+    """DBSCAN clustering of detections (Sec. 2.3) on a detection list shaped
+    like a 3-sigma pass over the paper-shaped plane (640 DMs x 59434
+    samples: about 54 000 background detections and five pulse bow-ties),
+    T_t = 16 samples, DM_t = 4 rows, SNR_t = 2, MinPts = 5.  One step = the
+    nine launches of one clustering; HIP events on the stream time them."""
+    import torch
+    import oracle
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    ndms, ns, te, de, se, mp = 640, 59434, 16, 4, 2.0, 5
+    s, d, q = synth.detections(ndms, ns, seed=1)
+    rec = np.zeros(len(s), A.CANDIDATE_DTYPE)
+    rec["dm_index"], rec["sample"], rec["snr"] = d, s, q
+    n = len(rec)
+    buf = torch.from_numpy(rec.view(np.uint8).copy()).cuda()
+    labels, nc = A.cluster_candidates(buf, n, ndms, te, de, se, mp)
+    nb = __import__("ctypes").c_size_t()
+    from paper_1307_5700_amd import _lib as L
+    L.check(L.lib().cluster_workspace_size(n, ndms, __import__("ctypes").byref(nb)), "cluster_workspace_size")
+    work = A._alloc(nb.value, buf.device)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        A.cluster_candidates(buf, n, ndms, te, de, se, mp, labels=labels, nclusters=nc, work=work)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    k_ms = e0.elapsed_time(e1) / args.steps
+    nclusters = int(nc.item())
+    nbytes = n * (24 + 4)                  # read every record once, write its label
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.cluster(s, d, q, te, de, se, mp)
+        reps += 1
+        if time.perf_counter() - t0 > min(args.cpu_seconds, 10.0):
+            break
+    cpu_s = (time.perf_counter() - t0) / reps
+    cfg = {"workload": "dbscan_640dm_59434samp_3sigma_detections", "ndms": ndms, "nsamps": ns, "points": n,
+           "t_eps": te, "dm_eps": de, "snr_eps": se, "min_pts": mp, "clusters": nclusters, "parallelism": "none"}
+    gbs = nbytes / (k_ms * 1e-3) / 1e9
+    extra = {"roofline": {"bound": "hbm", "kernel": "cluster chain (9 launches)", "achieved": gbs,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None},
+             "kernel_ms": k_ms}
+    if not args.no_cpu_baseline:
+        extra["cpu_baseline"] = {"value": n / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"the full list of {n} points, {reps} passes in {cpu_s * reps:.1f} s "
+                                           f"(numpy and scipy, one thread)"}
+    res = _line(n / dt, dt, args, "f32", cfg, extra)
+    res["metric"] = res["unit"] = "points/s"
     return res
 
 

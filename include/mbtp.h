@@ -286,6 +286,29 @@ mb_status mulaw_encode(const float* d_in, int64_t ld_in, int32_t nrows, int64_t 
 mb_status mulaw_decode(const uint8_t* d_codes, int64_t ld_codes, const float* d_xmax, int32_t nrows,
                        int64_t ncols, float mu, float* d_out, int64_t ld_out, void* stream);
 
+/* DBSCAN clustering of detections in (time, DM, SNR) (Sec. 2.3).  d_cands:
+ * n candidates in (dm_index, sample) order, as detect_candidates writes
+ * them, with 0 <= dm_index < ndms (other orders give unspecified labels).
+ * Candidate q is in the neighbourhood of p when |sample_q - sample_p| <=
+ * t_eps, |dm_index_q - dm_index_p| <= dm_eps and |snr_q - snr_p| <= snr_eps
+ * (the difference in FP32); p is in its own.  p is a core point when its
+ * neighbourhood holds at least min_pts candidates.  A cluster is a maximal
+ * set of core points linked through each other's neighbourhoods, plus the
+ * border points they reach; a border point reached from two clusters joins
+ * the one of its lowest-indexed core neighbour.  This is the exact result
+ * that the paper's FDBSCAN approximates.  d_labels [n] (device) receives
+ * -1 for noise and otherwise the cluster number, clusters numbered 0, 1, ...
+ * in order of their lowest-indexed core point; d_nclusters (device, one
+ * int32) the number of clusters.  d_work: cluster_workspace_size bytes,
+ * 256-byte aligned, caller-owned.  Asynchronous on stream; the result is a
+ * function of the input alone.  Errors: MB_EINVAL for n outside
+ * [0, 2^31 - 1024), ndms outside 1..65535, negative or non-finite extents,
+ * min_pts < 1, NULL or overlapping buffers, or a short workspace. */
+mb_status cluster_workspace_size(int64_t n, int32_t ndms, size_t* bytes);
+mb_status cluster_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps,
+                             float snr_eps, int32_t min_pts, int32_t* d_labels, int32_t* d_nclusters,
+                             void* d_work, size_t work_bytes, void* stream);
+
 /* 4+4-bit mu-law codec of 16-bit complex voltages (Sec. 2.4, Eq. 5), the
  * data writer's format for complex channelised series.  mulaw_encode_complex:
  * d_in holds nrows channel rows of (re, im) int16 pairs, row r at

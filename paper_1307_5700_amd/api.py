@@ -237,6 +237,29 @@ class Plan:
         return peaks.cpu().numpy().view(PEAK_DTYPE)
 
 
+def cluster_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_eps: int, snr_eps: float,
+                       min_pts: int, labels: torch.Tensor | None = None, nclusters: torch.Tensor | None = None,
+                       work: torch.Tensor | None = None, stream=None):
+    """DBSCAN clustering (Sec. 2.3) of the first n candidate records of a
+    device buffer in (dm_index, sample) order, as Plan.detect writes them:
+    returns (labels int32 [n], -1 for noise; nclusters int32 [1])."""
+    dev = cands.device
+    if cands.numel() < n * L.CANDIDATE_BYTES:
+        raise ValueError("cands holds fewer than n records")
+    labels = torch.empty(max(int(n), 1), dtype=torch.int32, device=dev) if labels is None else labels
+    nclusters = torch.empty(1, dtype=torch.int32, device=dev) if nclusters is None else nclusters
+    if labels.dtype != torch.int32 or labels.numel() < n or nclusters.dtype != torch.int32:
+        raise ValueError("labels must be int32 with room for n labels and nclusters int32")
+    if work is None:
+        nb = ctypes.c_size_t()
+        L.check(L.lib().cluster_workspace_size(int(n), int(ndms), ctypes.byref(nb)), "cluster_workspace_size")
+        work = _alloc(nb.value, dev)
+    L.check(L.lib().cluster_candidates(_ptr(cands), int(n), int(ndms), int(t_eps), int(dm_eps), float(snr_eps),
+                                       int(min_pts), _ptr(labels), _ptr(nclusters), _ptr(work), work.numel(),
+                                       _stream_ptr(stream)), "cluster_candidates")
+    return labels[:n], nclusters
+
+
 def median_filter(plane: torch.Tensor, ncols: int, half_width: int, out: torch.Tensor | None = None,
                   stream=None) -> torch.Tensor:
     """Windowed median filter (Sec. 2.2.3, Eq. 2) of the first `ncols`

@@ -31,6 +31,7 @@ SOURCES = {
     "median.hip": [],
     "mulaw.hip": [],
     "power.hip": [],
+    "cluster.hip": [],
     "mbtp.cpp": ["-x", "hip", "-ffp-contract=off"],
 }
 

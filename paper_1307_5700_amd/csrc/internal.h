@@ -216,6 +216,12 @@ hipError_t launch_mulaw_encode(const float* in, int64_t ld_in, int32_t nrows, in
                                uint8_t* codes, int64_t ld_codes, float* xmax, hipStream_t s);
 hipError_t launch_mulaw_decode(const uint8_t* codes, int64_t ld_codes, const float* xmax, int32_t nrows,
                                int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s);
+// DBSCAN clustering of detections (cluster.hip); the candidates are in
+// (dm_index, sample) order, n < 2^31.
+size_t cluster_work_bytes(int64_t n, int32_t ndms);
+hipError_t launch_cluster(const CandDev* c, int32_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps, float snr_eps,
+                          int32_t min_pts, int32_t* labels, int32_t* nclusters, void* work, hipStream_t s);
+
 // 4+4-bit codec of 16-bit complex voltages (mulaw.hip); ld_in, ncols and
 // ld_out count complex samples.
 hipError_t launch_mulaw_encode_complex(const int16_t* in, int64_t ld_in, int32_t nrows, int64_t ncols, float mu,

@@ -113,6 +113,45 @@ def voltages(nchans: int, nsamps: int, seed: int, sigma: float = 2000.0, clip_fr
     return v
 
 
+def detections(ndms: int, nsamps: int, seed: int, density: float = 1.35e-3, npulses: int = 5):
+    """A detection list shaped like an n-sigma pass over a dedispersed plane
+    at a low threshold: background detections scattered uniformly over the
+    (DM, sample) plane with the given density and exponential excess SNR
+    above 3, plus npulses bow-tie patterns (a pulse seen over neighbouring
+    DM rows, arriving earlier at higher DMs and weaker away from its DM).
+    Returns (sample int64, dm_index int32, snr float32), unique (dm, sample)
+    pairs in (dm_index, sample) order."""
+    rng = np.random.default_rng(seed)
+    k = rng.binomial(ndms * nsamps, density)
+    flat = rng.choice(ndms * nsamps, size=k, replace=False)
+    d = (flat // nsamps).astype(np.int64)
+    t = (flat % nsamps).astype(np.int64)
+    q = 3.0 + rng.exponential(0.35, k)
+    ds, ts, qs = [d], [t], [q]
+    for _ in range(npulses):
+        d0 = int(rng.integers(ndms // 8, ndms - ndms // 8))
+        t0 = int(rng.integers(64, nsamps - 64))
+        peak = float(rng.uniform(8.0, 30.0))
+        w = int(rng.integers(1, 17))
+        span = int(rng.integers(8, 40))
+        for dd in range(max(0, d0 - span), min(ndms, d0 + span + 1)):
+            off = -(dd - d0) // 2                       # earlier at higher DM
+            amp = peak / (1.0 + abs(dd - d0) / 6.0)
+            if amp < 3.0:
+                continue
+            for tt in range(t0 + off, t0 + off + w + abs(dd - d0) // 3):
+                if 0 <= tt < nsamps:
+                    ds.append(np.array([dd]))
+                    ts.append(np.array([tt]))
+                    qs.append(np.array([amp * (0.9 + 0.2 * rng.random())]))
+    d = np.concatenate(ds)
+    t = np.concatenate(ts)
+    q = np.concatenate(qs).astype(np.float32)
+    key = d * nsamps + t
+    _, first = np.unique(key, return_index=True)       # one detection per (dm, sample), in key order
+    return t[first], d[first].astype(np.int32), q[first]
+
+
 def quantise(v: np.ndarray, dtype: str) -> np.ndarray:
     if dtype == "f32":
         return np.ascontiguousarray(v, dtype=np.float32)

@@ -157,3 +157,33 @@ def test_mulaw_complex_rejects_bad_arguments():
     assert lib.mulaw_decode_complex(b, 100, x, 4, 100, 255.0, ctypes.c_void_p((1 << 30) - 64), 100,
                                     None) == L.MB_EINVAL                                          # overlap
     assert lib.mulaw_encode_complex(None, 0, 0, 100, 255.0, None, 0, None, None) == L.MB_OK        # no rows
+
+
+def test_cluster_rejects_bad_arguments():
+    L = _lib()
+    lib = L.lib()
+    nb = ctypes.c_size_t()
+    assert lib.cluster_workspace_size(1000, 640, ctypes.byref(nb)) == L.MB_OK and nb.value >= 16 * 1000
+    assert lib.cluster_workspace_size(-1, 640, ctypes.byref(nb)) == L.MB_EINVAL
+    assert lib.cluster_workspace_size(10, 0, ctypes.byref(nb)) == L.MB_EINVAL
+    lib.cluster_workspace_size(100, 64, ctypes.byref(nb))
+    c, lab, k, w = (ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31),
+                    ctypes.c_void_p(1 << 34))
+    ok = (c, 100, 64, 4, 2, 1.0, 3, lab, k, w, nb.value, None)
+
+    def call(**kw):
+        names = ["c", "n", "ndms", "te", "de", "se", "mp", "lab", "k", "w", "wb", "s"]
+        a = dict(zip(names, ok))
+        a.update(kw)
+        return lib.cluster_candidates(*[a[x] for x in names])
+    assert call(te=-1) == L.MB_EINVAL
+    assert call(de=-1) == L.MB_EINVAL
+    assert call(se=float("nan")) == L.MB_EINVAL
+    assert call(se=-1.0) == L.MB_EINVAL
+    assert call(mp=0) == L.MB_EINVAL
+    assert call(lab=None) == L.MB_EINVAL
+    assert call(k=None) == L.MB_EINVAL
+    assert call(wb=nb.value - 1) == L.MB_EINVAL                       # short workspace
+    assert call(w=ctypes.c_void_p((1 << 34) + 8)) == L.MB_EINVAL      # misaligned workspace
+    assert call(lab=ctypes.c_void_p((1 << 20) + 64)) == L.MB_EINVAL   # labels overlap candidates
+    assert call(ndms=0) == L.MB_EINVAL
