@@ -81,8 +81,8 @@ TRAFFIC = {
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
     "mulaw": ("mulaw_encode_kernel", "mulaw_traffic.txt", ("mulaw.hip", "internal.h"),
               "one mulaw_encode_kernel launch, mulaw workload (1024 ch x 65536 f32 power samples, mu 255)"),
-    "cluster": ("cluster_union_rows_kernel", "cluster_traffic.txt", ("cluster.hip", "internal.h"),
-                "one cluster_union_rows_kernel launch, cluster workload (53858 detections, 640 DMs)"),
+    "cluster": ("cluster_union_kernel", "cluster_traffic.txt", ("cluster.hip", "internal.h"),
+                "one cluster_union_kernel launch, cluster workload (53858 detections, 640 DMs)"),
     "power": ("power_kernel", "power_traffic.txt", ("power.hip", "internal.h"),
               "one power_kernel launch, power workload (1024 ch x 65536 int16 complex voltage samples)"),
 }
@@ -705,7 +705,7 @@ def bench_cluster(args):
     like a 3-sigma pass over the paper-shaped plane (640 DMs x 59434
     samples: about 54 000 background detections and five pulse bow-ties),
     T_t = 16 samples, DM_t = 4 rows, SNR_t = 2, MinPts = 5.  One step = the
-    nine launches of one clustering; HIP events on the stream time them."""
+    eleven launches of one clustering; HIP events on the stream time them."""
     import torch
     import oracle
     from paper_1307_5700_amd import api as A
@@ -751,7 +751,7 @@ def bench_cluster(args):
     cfg = {"workload": "dbscan_640dm_59434samp_3sigma_detections", "ndms": ndms, "nsamps": ns, "points": n,
            "t_eps": te, "dm_eps": de, "snr_eps": se, "min_pts": mp, "clusters": nclusters, "parallelism": "none"}
     gbs = nbytes / (k_ms * 1e-3) / 1e9
-    extra = {"roofline": {"bound": "hbm", "kernel": "cluster chain (9 launches)", "achieved": gbs,
+    extra = {"roofline": {"bound": "hbm", "kernel": "cluster chain (11 launches)", "achieved": gbs,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None},
              "kernel_ms": k_ms}
     if not args.no_cpu_baseline:

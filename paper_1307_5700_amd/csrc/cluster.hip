@@ -6,19 +6,22 @@
 // point q is a neighbour of p when it lies within t_eps samples, dm_eps DM
 // indices and snr_eps of SNR (the SNR difference in FP32), p included.
 //   1. row starts: one lower bound per DM index;
-//   2. neighbour counts: core points have at least min_pts;
+//   2. neighbour counts (one thread per point and DM row, summed with
+//      atomics): core points have at least min_pts;
 //   3. each core point hooked under its lowest core neighbour, then the
 //      union of core points with their lower-indexed core neighbours, in a
 //      lock-free union-find that always hooks the larger root under the
 //      smaller one, so every component's root is its lowest core index
 //      whatever the order of the unions (path halving keeps finds short);
 //   4. each core point takes its root; a border point takes the root of its
-//      lowest-indexed core neighbour; noise takes -1;
+//      lowest-indexed core neighbour (an atomic minimum over its rows); noise
+//      takes -1;
 //   5. the roots are numbered in index order (per-chunk counts, one
 //      workgroup's scan of them, per-root ranks) and the labels written.
 // Every result is a function of the input alone, bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -62,24 +65,6 @@ __device__ inline void for_row(const ClusterArgs& A, const CandDev& p, int32_t d
     if (fabsf(A.c[j].snr - p.snr) <= A.snr_eps) visit(j);
 }
 
-// Calls visit(j) for every neighbour j of point i, DM row by DM row.
-template <class F>
-__device__ inline void for_neighbours(const ClusterArgs& A, int32_t i, F&& visit) {
-  const CandDev p = A.c[i];
-  const int32_t d0 = max(p.dm_index - A.dm_eps, 0), d1 = min(p.dm_index + A.dm_eps, A.ndms - 1);
-  for (int32_t dd = d0; dd <= d1; ++dd) for_row(A, p, dd, visit);
-}
-
-__global__ __launch_bounds__(256) void cluster_count_kernel(ClusterArgs A, int32_t* __restrict__ core,
-                                                            int32_t* __restrict__ parent) {
-  const int32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= A.n) return;
-  int32_t cnt = 0;
-  for_neighbours(A, i, [&](int32_t) { ++cnt; });
-  core[i] = cnt >= A.min_pts ? 1 : 0;
-  parent[i] = i;
-}
-
 __device__ inline int32_t uf_load(int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -104,60 +89,88 @@ __device__ inline void uf_unite(int32_t* parent, int32_t a, int32_t b) {
   }
 }
 
+// The neighbourhood passes run one thread per (point, DM row of its
+// neighbourhood), grid-stride: a point inside a pulse's bow-tie has hundreds
+// of neighbours, and a thread per point would leave the pass as long as its
+// longest scan (for the unions, a chain of dependent L2 round trips per
+// neighbour).  Per-point results are combined with integer atomics, which
+// are order-independent.
+template <class F>
+__device__ inline void for_point_rows(const ClusterArgs& A, F&& body) {
+  const int64_t R = 2 * (int64_t)A.dm_eps + 1, total = (int64_t)A.n * R;
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int32_t i = (int32_t)(t / R);
+    const CandDev p = A.c[i];
+    const int64_t dd = (int64_t)p.dm_index - A.dm_eps + t % R;
+    if (dd < 0 || dd >= A.ndms) continue;
+    body(i, p, (int32_t)dd);
+  }
+}
+
+__global__ __launch_bounds__(256) void cluster_init_kernel(int32_t n, int32_t* __restrict__ cnt,
+                                                           int32_t* __restrict__ parent, int32_t* __restrict__ bmin) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  cnt[i] = 0;
+  parent[i] = i;
+  bmin[i] = n;
+}
+
+// Neighbour counts: cnt[i] >= min_pts makes i a core point.
+__global__ __launch_bounds__(256) void cluster_count_kernel(ClusterArgs A, int32_t* cnt) {
+  for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
+    int32_t k = 0;
+    for_row(A, p, dd, [&](int32_t) { ++k; });
+    if (k) atomicAdd(cnt + i, k);
+  });
+}
+
 // Points every core point at its lowest-indexed core neighbour (itself if
 // none is lower): a forest of real core-core edges, shallow for dense
 // clusters, so that the unions below mostly find their sets already joined.
-__global__ __launch_bounds__(256) void cluster_hook_kernel(ClusterArgs A, const int32_t* __restrict__ core,
-                                                           int32_t* __restrict__ parent) {
-  const int32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= A.n || !core[i]) return;
-  int32_t best = i;
-  for_neighbours(A, i, [&](int32_t j) {
-    if (j < best && core[j]) best = j;
+__global__ __launch_bounds__(256) void cluster_hook_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
+                                                           int32_t* parent) {
+  for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
+    if (cnt[i] < A.min_pts) return;
+    int32_t best = i;
+    for_row(A, p, dd, [&](int32_t j) {
+      if (j < best && cnt[j] >= A.min_pts) best = j;
+    });
+    if (best < i) atomicMin(parent + i, best);
   });
-  parent[i] = best;
 }
 
-__global__ __launch_bounds__(256) void cluster_union_kernel(ClusterArgs A, const int32_t* __restrict__ core,
+// Union of every core point with its lower-indexed core neighbours.
+__global__ __launch_bounds__(256) void cluster_union_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
                                                             int32_t* parent) {
-  const int32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= A.n || !core[i]) return;
-  for_neighbours(A, i, [&](int32_t j) {
-    if (j < i && core[j]) uf_unite(parent, i, j);
+  for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
+    if (cnt[i] < A.min_pts) return;
+    for_row(A, p, dd, [&](int32_t j) {
+      if (j < i && cnt[j] >= A.min_pts) uf_unite(parent, i, j);
+    });
   });
 }
 
-// The same unions with one thread per (point, DM row of its neighbourhood):
-// a point in a dense cluster has hundreds of neighbours, and each union is a
-// chain of dependent L2 round trips, so splitting the rows shortens the
-// longest thread by the row count.
-__global__ __launch_bounds__(256) void cluster_union_rows_kernel(ClusterArgs A, const int32_t* __restrict__ core,
-                                                                int32_t* parent) {
-  const int32_t R = 2 * A.dm_eps + 1;
-  const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-  const int32_t i = (int32_t)(t / R);
-  if (i >= A.n || !core[i]) return;
-  const CandDev p = A.c[i];
-  const int32_t dd = p.dm_index - A.dm_eps + (int32_t)(t % R);
-  if (dd < 0 || dd >= A.ndms) return;
-  for_row(A, p, dd, [&](int32_t j) {
-    if (j < i && core[j]) uf_unite(parent, i, j);
+// Lowest-indexed core neighbour of every non-core point (n if none).
+__global__ __launch_bounds__(256) void cluster_border_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
+                                                             int32_t* bmin) {
+  for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
+    if (cnt[i] >= A.min_pts) return;
+    int32_t best = A.n;
+    for_row(A, p, dd, [&](int32_t j) {
+      if (j < best && cnt[j] >= A.min_pts) best = j;
+    });
+    if (best < A.n) atomicMin(bmin + i, best);
   });
 }
 
-__global__ __launch_bounds__(256) void cluster_root_kernel(ClusterArgs A, const int32_t* __restrict__ core,
-                                                           int32_t* parent, int32_t* __restrict__ root) {
+__global__ __launch_bounds__(256) void cluster_root_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
+                                                           const int32_t* __restrict__ bmin, int32_t* parent,
+                                                           int32_t* __restrict__ root) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= A.n) return;
-  if (core[i]) {
-    root[i] = uf_find(parent, i);
-    return;
-  }
-  int32_t best = A.n;
-  for_neighbours(A, i, [&](int32_t j) {
-    if (core[j] && j < best) best = j;
-  });
-  root[i] = best < A.n ? uf_find(parent, best) : -1;
+  if (cnt[i] >= A.min_pts) root[i] = uf_find(parent, i);
+  else root[i] = bmin[i] < A.n ? uf_find(parent, bmin[i]) : -1;
 }
 
 // Numbering: roots per 256-point chunk, an exclusive scan of the chunk
@@ -255,18 +268,18 @@ hipError_t launch_cluster(const CandDev* c, int32_t n, int32_t ndms, int64_t t_e
   ClusterArgs A{c, n, ndms, dm_eps, t_eps, snr_eps, min_pts, row_start};
   const int32_t nchunks = (int32_t)((n + 255) / 256);
   const unsigned gn = (unsigned)nchunks;
+  const int64_t rows_threads = (int64_t)n * (2 * (int64_t)dm_eps + 1);
+  const unsigned gr = (unsigned)std::min<int64_t>((rows_threads + 255) / 256, int64_t(1) << 20);
+  int32_t* bmin = rank;                   // free until the numbering
   hipLaunchKernelGGL(cluster_rows_kernel, dim3((unsigned)((ndms + 1 + 255) / 256)), dim3(256), 0, s, c, n, ndms,
                      row_start);
   if (n > 0) {
-    hipLaunchKernelGGL(cluster_count_kernel, dim3(gn), dim3(256), 0, s, A, core, parent);
-    hipLaunchKernelGGL(cluster_hook_kernel, dim3(gn), dim3(256), 0, s, A, core, parent);
-    const int64_t rows_threads = (int64_t)n * (2 * (int64_t)dm_eps + 1);
-    if (rows_threads <= (int64_t(1) << 36))
-      hipLaunchKernelGGL(cluster_union_rows_kernel, dim3((unsigned)((rows_threads + 255) / 256)), dim3(256), 0, s, A,
-                         core, parent);
-    else
-      hipLaunchKernelGGL(cluster_union_kernel, dim3(gn), dim3(256), 0, s, A, core, parent);
-    hipLaunchKernelGGL(cluster_root_kernel, dim3(gn), dim3(256), 0, s, A, core, parent, root);
+    hipLaunchKernelGGL(cluster_init_kernel, dim3(gn), dim3(256), 0, s, n, core, parent, bmin);
+    hipLaunchKernelGGL(cluster_count_kernel, dim3(gr), dim3(256), 0, s, A, core);
+    hipLaunchKernelGGL(cluster_hook_kernel, dim3(gr), dim3(256), 0, s, A, core, parent);
+    hipLaunchKernelGGL(cluster_union_kernel, dim3(gr), dim3(256), 0, s, A, core, parent);
+    hipLaunchKernelGGL(cluster_border_kernel, dim3(gr), dim3(256), 0, s, A, core, bmin);
+    hipLaunchKernelGGL(cluster_root_kernel, dim3(gn), dim3(256), 0, s, A, core, bmin, parent, root);
     hipLaunchKernelGGL(cluster_chunk_count_kernel, dim3(gn), dim3(256), 0, s, n, root, chunk);
   }
   hipLaunchKernelGGL(cluster_chunk_scan_kernel, dim3(1), dim3(1024), 0, s, nchunks, chunk, nclusters);
