@@ -739,6 +739,18 @@ def bench_cluster(args):
     dt = (time.perf_counter() - t0) / args.steps
     k_ms = e0.elapsed_time(e1) / args.steps
     nclusters = int(nc.item())
+    # DM-SNR classification of the clusters (Eqs. 3-4), timed the same way
+    info = A.classify_clusters(buf, labels, n, nclusters, ndms, 0.0, 0.2, 51.2e-6, 20.0, 0.408)
+    for _ in range(args.warmup):
+        A.classify_clusters(buf, labels, n, nclusters, ndms, 0.0, 0.2, 51.2e-6, 20.0, 0.408, info=info)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        A.classify_clusters(buf, labels, n, nclusters, ndms, 0.0, 0.2, 51.2e-6, 20.0, 0.408, info=info)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    c_ms = e0.elapsed_time(e1) / args.steps
+    cls = info.cpu().numpy().view(A.CLUSTER_INFO_DTYPE)["cls"]
     nbytes = n * (24 + 4)                  # read every record once, write its label
     t0 = time.perf_counter()
     reps = 0
@@ -753,7 +765,10 @@ def bench_cluster(args):
     gbs = nbytes / (k_ms * 1e-3) / 1e9
     extra = {"roofline": {"bound": "hbm", "kernel": "cluster chain (11 launches)", "achieved": gbs,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None},
-             "kernel_ms": k_ms}
+             "kernel_ms": k_ms,
+             "classify": {"kernel_ms": c_ms, "clusters": nclusters, "candidates": int((cls == 0).sum()),
+                          "rfi_low_dm": int((cls == 1).sum()), "rfi_rmse": int((cls == 2).sum()),
+                          "k": 3, "rmse_max": 0.2, "dm_min": 1.0}}
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = {"value": n / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
                                  "sample": f"the full list of {n} points, {reps} passes in {cpu_s * reps:.1f} s "

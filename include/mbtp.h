@@ -309,6 +309,39 @@ mb_status cluster_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndm
                              float snr_eps, int32_t min_pts, int32_t* d_labels, int32_t* d_nclusters,
                              void* d_work, size_t work_bytes, void* stream);
 
+/* Per-cluster result of the DM-SNR classification. */
+typedef struct {
+  int32_t peak_dm_index;  /* row with the most detections (ties: larger SNR, then lower index) */
+  int32_t npoints;        /* detections carrying the label                                     */
+  int32_t ndm_rows;       /* DM rows holding any of them                                       */
+  int32_t cls;            /* 0 candidate, 1 peak DM below dm_min (broadband RFI),
+                             2 RMSE above rmse_max (RFI), 3 no detection carries the label     */
+  int64_t t_first, t_last;/* first and last sample at the peak row                            */
+  float peak_snr;         /* largest SNR at the peak row                                      */
+  int32_t reserved;
+  double rmse;            /* NaN for classes 1 and 3                                          */
+} mb_cluster_info;
+
+/* DM-SNR classification of clusters (Sec. 2.3, Eqs. 3-4), one workgroup per
+ * cluster.  d_cands [n] and d_labels [n] as cluster_candidates leaves them
+ * (0 <= dm_index < ndms); d_info [nclusters] receives one record per label
+ * 0..nclusters-1.  Per cluster: the signature is the largest SNR of every DM
+ * row holding its detections, in DM order; it is smoothed by a centred
+ * k-point moving average (truncated at the ends) and divided by its value at
+ * the peak row.  A peak DM (dm_start + index * dm_step) below dm_min gives
+ * class 1.  Otherwise the width W = (t_last - t_first + 1) * tsamp_s and the
+ * curve sqrt(pi)/2 * erf(z)/z, z = 6.91e-3 * dDM * bw_mhz / (W_ms * f_ghz^3)
+ * (bw_mhz the band's width, f_ghz its centre) give the model at each row's
+ * DM error from the peak; the RMSE between the two decides class 0 (at most
+ * rmse_max) or 2.  Arithmetic in FP64.  Device buffers owned by the caller.
+ * Asynchronous on stream.  Errors: MB_EINVAL for sizes out of range, ndms
+ * above 4000, an even k, non-positive or non-finite tsamp/bandwidth/
+ * frequency, or NULL buffers. */
+mb_status classify_clusters(const mb_candidate* d_cands, const int32_t* d_labels, int64_t n, int32_t nclusters,
+                            int32_t ndms, double dm_start, double dm_step, double tsamp_s, double bw_mhz,
+                            double f_ghz, int32_t k, double rmse_max, double dm_min, mb_cluster_info* d_info,
+                            void* stream);
+
 /* 4+4-bit mu-law codec of 16-bit complex voltages (Sec. 2.4, Eq. 5), the
  * data writer's format for complex channelised series.  mulaw_encode_complex:
  * d_in holds nrows channel rows of (re, im) int16 pairs, row r at

@@ -86,6 +86,9 @@ _SIGS = {
     "cluster_workspace_size": ([c_i64, c_i32, ctypes.POINTER(ctypes.c_size_t)], c_i32),
     "cluster_candidates": ([c_vp, c_i64, c_i32, c_i64, c_i32, ctypes.c_float, c_i32, c_vp, c_vp, c_vp,
                             ctypes.c_size_t, c_vp], c_i32),
+    "classify_clusters": ([c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, c_i32, ctypes.c_double, ctypes.c_double, c_vp, c_vp],
+                          c_i32),
     "mulaw_encode_complex": ([c_vp, c_i64, c_i32, c_i64, ctypes.c_float, c_vp, c_i64, c_vp, c_vp], c_i32),
     "mulaw_decode_complex": ([c_vp, c_i64, c_vp, c_i32, c_i64, ctypes.c_float, c_vp, c_i64, c_vp], c_i32),
     "dedisp_beam_create": ([c_vp, ctypes.POINTER(c_vp)], c_i32),

@@ -260,6 +260,29 @@ def cluster_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_ep
     return labels[:n], nclusters
 
 
+CLUSTER_INFO_DTYPE = np.dtype([("peak_dm_index", "<i4"), ("npoints", "<i4"), ("ndm_rows", "<i4"), ("cls", "<i4"),
+                               ("t_first", "<i8"), ("t_last", "<i8"), ("peak_snr", "<f4"), ("reserved", "<i4"),
+                               ("rmse", "<f8")])
+
+
+def classify_clusters(cands: torch.Tensor, labels: torch.Tensor, n: int, nclusters: int, ndms: int,
+                      dm_start: float, dm_step: float, tsamp_s: float, bw_mhz: float, f_ghz: float, k: int = 3,
+                      rmse_max: float = 0.2, dm_min: float = 1.0, info: torch.Tensor | None = None, stream=None):
+    """DM-SNR classification (Sec. 2.3, Eqs. 3-4) of clusters 0..nclusters-1
+    of the first n candidate records: returns a uint8 device buffer of
+    nclusters CLUSTER_INFO_DTYPE records."""
+    rec = CLUSTER_INFO_DTYPE.itemsize
+    if info is None:
+        info = torch.empty(max(int(nclusters), 1) * rec, dtype=torch.uint8, device=cands.device)
+    if info.dtype != torch.uint8 or info.numel() < nclusters * rec:
+        raise ValueError("info must be a uint8 buffer of nclusters records")
+    L.check(L.lib().classify_clusters(_ptr(cands), _ptr(labels), int(n), int(nclusters), int(ndms), float(dm_start),
+                                      float(dm_step), float(tsamp_s), float(bw_mhz), float(f_ghz), int(k),
+                                      float(rmse_max), float(dm_min), _ptr(info), _stream_ptr(stream)),
+            "classify_clusters")
+    return info
+
+
 def median_filter(plane: torch.Tensor, ncols: int, half_width: int, out: torch.Tensor | None = None,
                   stream=None) -> torch.Tensor:
     """Windowed median filter (Sec. 2.2.3, Eq. 2) of the first `ncols`

@@ -243,7 +243,188 @@ __global__ __launch_bounds__(256) void cluster_label_kernel(int32_t n, const int
   labels[i] = r < 0 ? -1 : rank[r];
 }
 
+// ---- DM-SNR classification of clusters (Eqs. 3-4) ---------------------------
+// One 256-thread workgroup per cluster.  LDS holds, per DM row, the count
+// and the largest SNR of the cluster's detections (an order-preserving int
+// key for atomicMax), then the compacted sequence of rows that hold any.
+struct ClusterInfoDev {
+  int32_t peak_dm_index, npoints, ndm_rows, cls;
+  int64_t t_first, t_last;
+  float peak_snr;
+  int32_t reserved;
+  double rmse;
+};
+
+struct ClassifyArgs {
+  const CandDev* c;
+  const int32_t* labels;
+  int32_t n, ndms, k;
+  double dm_start, dm_step, tsamp_s, bw_mhz, f_ghz, rmse_max, dm_min;
+  ClusterInfoDev* info;
+};
+
+__device__ inline int32_t snr_key(float x) {
+  const int32_t b = __float_as_int(x);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ inline float snr_of_key(int32_t k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+// (count, snr key, -dm) lexicographic maximum
+__device__ inline bool peak_better(int32_t c1, int32_t k1, int32_t d1, int32_t c2, int32_t k2, int32_t d2) {
+  if (c1 != c2) return c1 > c2;
+  if (k1 != k2) return k1 > k2;
+  return d1 < d2;
+}
+
+__device__ inline int64_t shfl_xor64(int64_t v, int m) {
+  const int32_t lo = __shfl_xor((int32_t)(v & 0xffffffff), m, 64), hi = __shfl_xor((int32_t)(v >> 32), m, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
+  extern __shared__ int32_t lds[];
+  int32_t* cnt = lds;                       // [ndms]
+  int32_t* skey = lds + A.ndms;             // [ndms]
+  int32_t* seqd = lds + 2 * A.ndms;         // [ndms]
+  float* seqv = reinterpret_cast<float*>(lds + 3 * A.ndms);   // [ndms]
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t wc[4], wk[4], wd[4], npts_s[4];
+  __shared__ int64_t wlo[4], whi[4];
+  __shared__ double wsq[4];
+  __shared__ int32_t peak_s, ppos_s, nrows_s;
+  const int32_t cl = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int32_t d = tid; d < A.ndms; d += 256) { cnt[d] = 0; skey[d] = INT32_MIN; }
+  __syncthreads();
+  int32_t np = 0;
+  for (int32_t i = tid; i < A.n; i += 256) {
+    if (A.labels[i] != cl) continue;
+    const int32_t d = A.c[i].dm_index;
+    if (d < 0 || d >= A.ndms) continue;
+    atomicAdd(cnt + d, 1);
+    atomicMax(skey + d, snr_key(A.c[i].snr));
+    ++np;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) np += __shfl_xor(np, off, 64);
+  if (lane == 0) npts_s[w] = np;
+  __syncthreads();
+  // peak row
+  int32_t bc = -1, bk = INT32_MIN, bd = A.ndms;
+  for (int32_t d = tid; d < A.ndms; d += 256)
+    if (cnt[d] > 0 && peak_better(cnt[d], skey[d], d, bc, bk, bd)) { bc = cnt[d]; bk = skey[d]; bd = d; }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int32_t c2 = __shfl_xor(bc, off, 64), k2 = __shfl_xor(bk, off, 64), d2 = __shfl_xor(bd, off, 64);
+    if (peak_better(c2, k2, d2, bc, bk, bd)) { bc = c2; bk = k2; bd = d2; }
+  }
+  if (lane == 0) { wc[w] = bc; wk[w] = bk; wd[w] = bd; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 1; k < 4; ++k)
+      if (peak_better(wc[k], wk[k], wd[k], wc[0], wk[0], wd[0])) { wc[0] = wc[k]; wk[0] = wk[k]; wd[0] = wd[k]; }
+    peak_s = wd[0];
+  }
+  __syncthreads();
+  const int32_t peak = peak_s;
+  ClusterInfoDev* rec = A.info + cl;
+  if (peak >= A.ndms) {                     // no detection carries this label
+    if (tid == 0) {
+      rec->peak_dm_index = -1; rec->npoints = 0; rec->ndm_rows = 0; rec->cls = 3;
+      rec->t_first = 0; rec->t_last = 0; rec->peak_snr = 0.0f; rec->reserved = 0; rec->rmse = __builtin_nan("");
+    }
+    return;
+  }
+  // first and last sample at the peak row
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  for (int32_t i = tid; i < A.n; i += 256)
+    if (A.labels[i] == cl && A.c[i].dm_index == peak) {
+      const int64_t t = A.c[i].sample;
+      lo = t < lo ? t : lo;
+      hi = t > hi ? t : hi;
+    }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int64_t l2 = shfl_xor64(lo, off), h2 = shfl_xor64(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (lane == 0) { wlo[w] = lo; whi[w] = hi; }
+  // compacted sequence of rows holding detections
+  int32_t carry = 0;
+  for (int32_t base = 0; base < A.ndms; base += 256) {
+    const int32_t d = base + tid;
+    const int32_t f = (d < A.ndms && cnt[d] > 0) ? 1 : 0;
+    int32_t total;
+    const int32_t ex = block_exclusive(f, wsum, total);
+    if (f) {
+      seqd[carry + ex] = d;
+      seqv[carry + ex] = snr_of_key(skey[d]);
+      if (d == peak) ppos_s = carry + ex;
+    }
+    carry += total;
+    __syncthreads();
+  }
+  if (tid == 0) nrows_s = carry;
+  __syncthreads();
+  const int32_t L = nrows_s, pp = ppos_s;
+  if (tid == 0) {
+    int64_t l = wlo[0], h = whi[0];
+    for (int k = 1; k < 4; ++k) { l = wlo[k] < l ? wlo[k] : l; h = whi[k] > h ? whi[k] : h; }
+    rec->peak_dm_index = peak;
+    rec->npoints = npts_s[0] + npts_s[1] + npts_s[2] + npts_s[3];
+    rec->ndm_rows = L;
+    rec->t_first = l;
+    rec->t_last = h;
+    rec->peak_snr = snr_of_key(skey[peak]);
+    rec->reserved = 0;
+    wlo[0] = l;
+    whi[0] = h;
+  }
+  __syncthreads();
+  if (A.dm_start + peak * A.dm_step < A.dm_min) {
+    if (tid == 0) { rec->cls = 1; rec->rmse = __builtin_nan(""); }
+    return;
+  }
+  const int32_t hw = (A.k - 1) / 2;
+  auto smooth = [&](int32_t p) {
+    const int32_t a = p - hw < 0 ? 0 : p - hw, b = p + hw + 1 > L ? L : p + hw + 1;
+    double sum = 0.0;
+    for (int32_t j = a; j < b; ++j) sum += (double)seqv[j];
+    return sum / (double)(b - a);
+  };
+  const double sp = smooth(pp);
+  const double width_ms = (double)(whi[0] - wlo[0] + 1) * A.tsamp_s * 1e3;
+  const double f3 = A.f_ghz * A.f_ghz * A.f_ghz;
+  double sq = 0.0;
+  for (int32_t p = tid; p < L; p += 256) {
+    const double norm = smooth(p) / sp;
+    const double ddm = (double)(seqd[p] - peak) * A.dm_step;
+    const double z = fabs(6.91e-3 * ddm * A.bw_mhz / (width_ms * f3));
+    const double model = z > 0.0 ? 0.88622692545275801 * erf(z) / z : 1.0;   // sqrt(pi) / 2
+    sq += (norm - model) * (norm - model);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+  if (lane == 0) wsq[w] = sq;
+  __syncthreads();
+  if (tid == 0) {
+    const double rmse = sqrt((wsq[0] + wsq[1] + wsq[2] + wsq[3]) / (double)L);
+    rec->rmse = rmse;
+    rec->cls = rmse <= A.rmse_max ? 0 : 2;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_classify(const CandDev* c, const int32_t* labels, int32_t n, int32_t nclusters, int32_t ndms,
+                           double dm_start, double dm_step, double tsamp_s, double bw_mhz, double f_ghz, int32_t k,
+                           double rmse_max, double dm_min, void* info, hipStream_t s) {
+  if (nclusters == 0) return hipSuccess;
+  ClassifyArgs A{c, labels, n, ndms, k, dm_start, dm_step, tsamp_s, bw_mhz, f_ghz, rmse_max, dm_min,
+                 static_cast<ClusterInfoDev*>(info)};
+  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)nclusters), dim3(256), 16 * (size_t)ndms, s, A);
+  return hipGetLastError();
+}
 
 size_t cluster_work_bytes(int64_t n, int32_t ndms) {
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };

@@ -127,6 +127,7 @@ int32_t span_max(const mb_plan& p, int BD) {
 // kernels (chunk, ring and staging margin) inside 32 bits
 constexpr int64_t kMaxSamps = int64_t(1) << 30;
 constexpr int32_t kMaxDms = 65535;                 // DM trials of one plan
+constexpr int32_t kMaxClassifyDms = 4000;          // per-row tables of one cluster in 64 KB of LDS
 constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, less the persistent kernel's static LDS
 
 // LDS copy length: the largest window start (span + 3, rounded down to 4)
@@ -808,6 +809,35 @@ mb_status cluster_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndm
     return fail(MB_EINVAL, "candidates, labels and work must not overlap");
   HIP_TRY(launch_cluster(reinterpret_cast<const CandDev*>(d_cands), (int32_t)n, ndms, t_eps, dm_eps, snr_eps, min_pts,
                          d_labels, d_nclusters, d_work, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+// Defined with the clustering kernels (cluster.hip).
+extern "C++" {
+namespace mbtp {
+hipError_t launch_classify(const CandDev* c, const int32_t* labels, int32_t n, int32_t nclusters, int32_t ndms,
+                           double dm_start, double dm_step, double tsamp_s, double bw_mhz, double f_ghz, int32_t k,
+                           double rmse_max, double dm_min, void* info, hipStream_t s);
+}
+}
+
+mb_status classify_clusters(const mb_candidate* d_cands, const int32_t* d_labels, int64_t n, int32_t nclusters,
+                            int32_t ndms, double dm_start, double dm_step, double tsamp_s, double bw_mhz,
+                            double f_ghz, int32_t k, double rmse_max, double dm_min, mb_cluster_info* d_info,
+                            void* stream) {
+  static_assert(sizeof(mb_cluster_info) == 48, "cluster record layout");
+  if (n < 0 || n > 2147483647 - 1024) return fail(MB_EINVAL, "n must be in [0, 2^31 - 1024)");
+  if (nclusters < 0) return fail(MB_EINVAL, "nclusters must be >= 0");
+  if (ndms < 1 || ndms > kMaxClassifyDms) return fail(MB_EINVAL, "ndms must be in [1, %d]", kMaxClassifyDms);
+  if (k < 1 || k % 2 == 0) return fail(MB_EINVAL, "k must be odd and >= 1");
+  if (!(tsamp_s > 0.0) || !(bw_mhz > 0.0) || !(f_ghz > 0.0) || !isfinite(tsamp_s) || !isfinite(bw_mhz) ||
+      !isfinite(f_ghz) || !isfinite(dm_start) || !isfinite(dm_step) || !isfinite(dm_min) || std::isnan(rmse_max))
+    return fail(MB_EINVAL, "tsamp, bandwidth and frequency must be finite and > 0; DM values finite");
+  if (nclusters == 0) return ok();
+  if (!d_info || (n > 0 && (!d_cands || !d_labels))) return fail(MB_EINVAL, "buffers must not be NULL");
+  HIP_TRY(mbtp::launch_classify(reinterpret_cast<const CandDev*>(d_cands), d_labels, (int32_t)n, nclusters, ndms, dm_start,
+                          dm_step, tsamp_s, bw_mhz, f_ghz, k, rmse_max, dm_min, d_info,
+                          static_cast<hipStream_t>(stream)));
   return ok();
 }
 

@@ -187,3 +187,26 @@ def test_cluster_rejects_bad_arguments():
     assert call(w=ctypes.c_void_p((1 << 34) + 8)) == L.MB_EINVAL      # misaligned workspace
     assert call(lab=ctypes.c_void_p((1 << 20) + 64)) == L.MB_EINVAL   # labels overlap candidates
     assert call(ndms=0) == L.MB_EINVAL
+
+
+def test_classify_rejects_bad_arguments():
+    L = _lib()
+    lib = L.lib()
+    c, lab, info = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 34)
+    names = ["c", "lab", "n", "k", "ndms", "d0", "dd", "ts", "bw", "f", "kk", "rm", "dmin", "info", "s"]
+    ok = dict(zip(names, (c, lab, 100, 4, 640, 0.0, 0.2, 51.2e-6, 20.0, 0.408, 3, 0.2, 1.0, info, None)))
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return lib.classify_clusters(*[a[x] for x in names])
+    assert call(kk=2) == L.MB_EINVAL                   # even k
+    assert call(kk=0) == L.MB_EINVAL
+    assert call(ndms=4001) == L.MB_EINVAL              # per-row tables beyond 64 KB of LDS
+    assert call(ts=0.0) == L.MB_EINVAL
+    assert call(bw=float("inf")) == L.MB_EINVAL
+    assert call(f=-1.0) == L.MB_EINVAL
+    assert call(info=None) == L.MB_EINVAL
+    assert call(lab=None) == L.MB_EINVAL
+    assert call(k=-1) == L.MB_EINVAL
+    assert call(k=0, info=None) == L.MB_OK             # no clusters: nothing to do
