@@ -246,3 +246,32 @@ def test_cluster_mutants_fail_pins():
     s2, d2, q2 = [0, 1, 2, 0, 1, 2], [0, 0, 0, 9, 9, 9], [7.0] * 6
     assert list(oracle.cluster(s2, d2, q2, 2, 1, 1.0, 3)[0]) == [0, 0, 0, 1, 1, 1]
     assert _cluster_mutant(s2, d2, q2, 2, 1, 1.0, 3, ignore_dm=True)[0] != [0, 0, 0, 1, 1, 1]
+
+
+def test_classify_mutants_fail_pins():
+    """Slips in the DM-SNR classification: erf(z)/z without the sqrt(pi)/2
+    factor, z without the cube of the frequency, the peak row by SNR instead
+    of count, normalising by the signature's maximum instead of the peak
+    row, a one-sided moving average; each changes a pinned value."""
+    TS, BW, FC = 51.2e-6, 20.0, 0.408
+    w = 1.5
+    z = 6.91e-3 * 1.0 * BW / (w * FC ** 3)
+    good = oracle.dm_error_response([1.0], w, BW, FC)[0]
+    assert abs(good - math.sqrt(math.pi) / 2 * math.erf(z) / z) < 1e-15
+    assert abs(math.erf(z) / z - good) > 1e-3                                   # factor dropped
+    z1 = 6.91e-3 * 1.0 * BW / (w * FC)
+    assert abs(math.sqrt(math.pi) / 2 * math.erf(z1) / z1 - good) > 1e-3        # no cube
+    # rows 5, 6, 7 with counts 2, 1, 3 and maxima 4, 9, 1.5: the peak by count is row 7 (by SNR: row 6)
+    s = np.array([0, 1, 0, 0, 1, 2])
+    d = np.array([5, 5, 6, 7, 7, 7])
+    q = np.array([4.0, 4.0, 9.0, 1.5, 1.5, 1.5], np.float32)
+    info = oracle.classify_clusters(s, d, q, np.zeros(6, np.int32), 1, 10.0, 1.0, TS, BW, FC, k=3, rmse_max=10)
+    assert info[0]["peak_dm_index"] == 7
+    # smoothed [6.5, 14.5/3, 5.25], normalised at the peak row (5.25), not by the maximum (6.5, row 5)
+    sm = np.array([(4 + 9) / 2, (4 + 9 + 1.5) / 3, (9 + 1.5) / 2])
+    model = oracle.dm_error_response(np.array([-2.0, -1.0, 0.0]), 3 * TS * 1e3, BW, FC)
+    want = math.sqrt(np.mean((sm / sm[2] - model) ** 2))
+    assert abs(info[0]["rmse"] - want) < 1e-15
+    assert abs(math.sqrt(np.mean((sm / sm.max() - model) ** 2)) - want) > 1e-3
+    one_sided = np.array([4.0, (4 + 9) / 2, (4 + 9 + 1.5) / 3])
+    assert abs(math.sqrt(np.mean((one_sided / one_sided[2] - model) ** 2)) - want) > 1e-3
