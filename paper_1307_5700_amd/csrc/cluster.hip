@@ -79,13 +79,15 @@ __device__ inline int32_t uf_find(int32_t* parent, int32_t x) {
   }
 }
 
-__device__ inline void uf_unite(int32_t* parent, int32_t a, int32_t b) {
+// Joins the sets of a and b; returns the root the joined set had when the
+// join (or the finding that they were joined) took effect.
+__device__ inline int32_t uf_unite(int32_t* parent, int32_t a, int32_t b) {
   while (true) {
     a = uf_find(parent, a);
     b = uf_find(parent, b);
-    if (a == b) return;
+    if (a == b) return a;
     if (a < b) { const int32_t t = a; a = b; b = t; }
-    if (atomicCAS(parent + a, a, b) == a) return;   // a was still a root: hooked under b
+    if (atomicCAS(parent + a, a, b) == a) return b;   // a was still a root: hooked under b
   }
 }
 
@@ -145,8 +147,11 @@ __global__ __launch_bounds__(256) void cluster_union_kernel(ClusterArgs A, const
                                                             int32_t* parent) {
   for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
     if (cnt[i] < A.min_pts) return;
+    // i's root, kept from one union to the next: sets only ever merge, so a
+    // neighbour whose root was ever seen equal to it is already joined
+    int32_t ri = uf_find(parent, i);
     for_row(A, p, dd, [&](int32_t j) {
-      if (j < i && cnt[j] >= A.min_pts) uf_unite(parent, i, j);
+      if (j < i && cnt[j] >= A.min_pts && uf_find(parent, j) != ri) ri = uf_unite(parent, ri, j);
     });
   });
 }
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(256) void cluster_label_kernel(int32_t n, const int
 }
 
 // ---- DM-SNR classification of clusters (Eqs. 3-4) ---------------------------
-// One 256-thread workgroup per cluster.  LDS holds, per DM row, the count
+// One 1024-thread workgroup per cluster.  LDS holds, per DM row, the count
 // and the largest SNR of the cluster's detections (an order-preserving int
 // key for atomicMax), then the compacted sequence of rows that hold any.
 struct ClusterInfoDev {
@@ -281,22 +286,22 @@ __device__ inline int64_t shfl_xor64(int64_t v, int m) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
+__global__ __launch_bounds__(1024) void classify_kernel(ClassifyArgs A) {
   extern __shared__ int32_t lds[];
   int32_t* cnt = lds;                       // [ndms]
   int32_t* skey = lds + A.ndms;             // [ndms]
   int32_t* seqd = lds + 2 * A.ndms;         // [ndms]
   float* seqv = reinterpret_cast<float*>(lds + 3 * A.ndms);   // [ndms]
-  __shared__ int32_t wsum[4];
-  __shared__ int32_t wc[4], wk[4], wd[4], npts_s[4];
-  __shared__ int64_t wlo[4], whi[4];
-  __shared__ double wsq[4];
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t wc[16], wk[16], wd[16], npts_s[16];
+  __shared__ int64_t wlo[16], whi[16];
+  __shared__ double wsq[16];
   __shared__ int32_t peak_s, ppos_s, nrows_s;
   const int32_t cl = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int32_t d = tid; d < A.ndms; d += 256) { cnt[d] = 0; skey[d] = INT32_MIN; }
+  for (int32_t d = tid; d < A.ndms; d += 1024) { cnt[d] = 0; skey[d] = INT32_MIN; }
   __syncthreads();
   int32_t np = 0;
-  for (int32_t i = tid; i < A.n; i += 256) {
+  for (int32_t i = tid; i < A.n; i += 1024) {
     if (A.labels[i] != cl) continue;
     const int32_t d = A.c[i].dm_index;
     if (d < 0 || d >= A.ndms) continue;
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   __syncthreads();
   // peak row
   int32_t bc = -1, bk = INT32_MIN, bd = A.ndms;
-  for (int32_t d = tid; d < A.ndms; d += 256)
+  for (int32_t d = tid; d < A.ndms; d += 1024)
     if (cnt[d] > 0 && peak_better(cnt[d], skey[d], d, bc, bk, bd)) { bc = cnt[d]; bk = skey[d]; bd = d; }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   if (lane == 0) { wc[w] = bc; wk[w] = bk; wd[w] = bd; }
   __syncthreads();
   if (tid == 0) {
-    for (int k = 1; k < 4; ++k)
+    for (int k = 1; k < 16; ++k)
       if (peak_better(wc[k], wk[k], wd[k], wc[0], wk[0], wd[0])) { wc[0] = wc[k]; wk[0] = wk[k]; wd[0] = wd[k]; }
     peak_s = wd[0];
   }
@@ -336,7 +341,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   }
   // first and last sample at the peak row
   int64_t lo = INT64_MAX, hi = INT64_MIN;
-  for (int32_t i = tid; i < A.n; i += 256)
+  for (int32_t i = tid; i < A.n; i += 1024)
     if (A.labels[i] == cl && A.c[i].dm_index == peak) {
       const int64_t t = A.c[i].sample;
       lo = t < lo ? t : lo;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   if (lane == 0) { wlo[w] = lo; whi[w] = hi; }
   // compacted sequence of rows holding detections
   int32_t carry = 0;
-  for (int32_t base = 0; base < A.ndms; base += 256) {
+  for (int32_t base = 0; base < A.ndms; base += 1024) {
     const int32_t d = base + tid;
     const int32_t f = (d < A.ndms && cnt[d] > 0) ? 1 : 0;
     int32_t total;
@@ -369,9 +374,11 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   const int32_t L = nrows_s, pp = ppos_s;
   if (tid == 0) {
     int64_t l = wlo[0], h = whi[0];
-    for (int k = 1; k < 4; ++k) { l = wlo[k] < l ? wlo[k] : l; h = whi[k] > h ? whi[k] : h; }
+    for (int k = 1; k < 16; ++k) { l = wlo[k] < l ? wlo[k] : l; h = whi[k] > h ? whi[k] : h; }
     rec->peak_dm_index = peak;
-    rec->npoints = npts_s[0] + npts_s[1] + npts_s[2] + npts_s[3];
+    int32_t np_all = 0;
+    for (int k = 0; k < 16; ++k) np_all += npts_s[k];
+    rec->npoints = np_all;
     rec->ndm_rows = L;
     rec->t_first = l;
     rec->t_last = h;
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   const double width_ms = (double)(whi[0] - wlo[0] + 1) * A.tsamp_s * 1e3;
   const double f3 = A.f_ghz * A.f_ghz * A.f_ghz;
   double sq = 0.0;
-  for (int32_t p = tid; p < L; p += 256) {
+  for (int32_t p = tid; p < L; p += 1024) {
     const double norm = smooth(p) / sp;
     const double ddm = (double)(seqd[p] - peak) * A.dm_step;
     const double z = fabs(6.91e-3 * ddm * A.bw_mhz / (width_ms * f3));
@@ -408,7 +415,9 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs A) {
   if (lane == 0) wsq[w] = sq;
   __syncthreads();
   if (tid == 0) {
-    const double rmse = sqrt((wsq[0] + wsq[1] + wsq[2] + wsq[3]) / (double)L);
+    double sum = 0.0;
+    for (int k = 0; k < 16; ++k) sum += wsq[k];
+    const double rmse = sqrt(sum / (double)L);
     rec->rmse = rmse;
     rec->cls = rmse <= A.rmse_max ? 0 : 2;
   }
@@ -422,7 +431,7 @@ hipError_t launch_classify(const CandDev* c, const int32_t* labels, int32_t n, i
   if (nclusters == 0) return hipSuccess;
   ClassifyArgs A{c, labels, n, ndms, k, dm_start, dm_step, tsamp_s, bw_mhz, f_ghz, rmse_max, dm_min,
                  static_cast<ClusterInfoDev*>(info)};
-  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)nclusters), dim3(256), 16 * (size_t)ndms, s, A);
+  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)nclusters), dim3(1024), 16 * (size_t)ndms, s, A);
   return hipGetLastError();
 }
 
