@@ -717,10 +717,7 @@ def bench_cluster(args):
     n = len(rec)
     buf = torch.from_numpy(rec.view(np.uint8).copy()).cuda()
     labels, nc = A.cluster_candidates(buf, n, ndms, te, de, se, mp)
-    nb = __import__("ctypes").c_size_t()
-    from paper_1307_5700_amd import _lib as L
-    L.check(L.lib().cluster_workspace_size(n, ndms, __import__("ctypes").byref(nb)), "cluster_workspace_size")
-    work = A._alloc(nb.value, buf.device)
+    work = A.alloc_cluster_work(n, ndms, buf.device)
     stream = torch.cuda.current_stream()
 
     def step():

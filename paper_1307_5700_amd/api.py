@@ -237,6 +237,13 @@ class Plan:
         return peaks.cpu().numpy().view(PEAK_DTYPE)
 
 
+def alloc_cluster_work(n: int, ndms: int, device) -> torch.Tensor:
+    """Device workspace of cluster_candidates for n detections and ndms rows."""
+    nb = ctypes.c_size_t()
+    L.check(L.lib().cluster_workspace_size(int(n), int(ndms), ctypes.byref(nb)), "cluster_workspace_size")
+    return _alloc(nb.value, device)
+
+
 def cluster_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_eps: int, snr_eps: float,
                        min_pts: int, labels: torch.Tensor | None = None, nclusters: torch.Tensor | None = None,
                        work: torch.Tensor | None = None, stream=None):
@@ -251,9 +258,7 @@ def cluster_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_ep
     if labels.dtype != torch.int32 or labels.numel() < n or nclusters.dtype != torch.int32:
         raise ValueError("labels must be int32 with room for n labels and nclusters int32")
     if work is None:
-        nb = ctypes.c_size_t()
-        L.check(L.lib().cluster_workspace_size(int(n), int(ndms), ctypes.byref(nb)), "cluster_workspace_size")
-        work = _alloc(nb.value, dev)
+        work = alloc_cluster_work(n, ndms, dev)
     L.check(L.lib().cluster_candidates(_ptr(cands), int(n), int(ndms), int(t_eps), int(dm_eps), float(snr_eps),
                                        int(min_pts), _ptr(labels), _ptr(nclusters), _ptr(work), work.numel(),
                                        _stream_ptr(stream)), "cluster_candidates")
