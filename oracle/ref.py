@@ -18,6 +18,7 @@ Readings of passages where the paper is silent or ambiguous are marked
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import math
 import os
@@ -110,16 +111,18 @@ class RfiParams:
     window:     W_c, the channel-chunk width in samples (reading: 256).
     k_mask, k_chan, k_spec: threshold factors in units of the relevant noise
                 std (reading: 5 each, matching a "5 sigma" RFI threshold).
-    mask_passes: how many fit-and-mask rounds pick the channels to interpolate
-                before the final fit (reading: 1; more rounds catch bright
-                channels hidden by brighter ones in the first RMSE).
+    mask_passes: the most fit-and-mask rounds that pick the channels to
+                interpolate before the final fit; rounds stop early once one
+                masks no new channel (reading: masking runs until it settles,
+                capped at 8, so a bright channel cannot hide a fainter one
+                behind the first fit's RMSE; 1 gives a single round).
     """
     poly_order: int = 3
     window: int = 256
     k_mask: float = 5.0
     k_chan: float = 5.0
     k_spec: float = 5.0
-    mask_passes: int = 1
+    mask_passes: int = 8
 
 
 @dataclass
@@ -180,6 +183,58 @@ def interpolate_masked(B: np.ndarray, masked: np.ndarray) -> np.ndarray:
     return out
 
 
+@dataclass
+class BandpassFit:
+    masked: np.ndarray            # bool[C], channels replaced by neighbour mean
+    bandpass_interp: np.ndarray   # B~[c] after masking
+    fit: np.ndarray               # f[c], fitted bandpass
+    residual0: np.ndarray         # B - first fit (mask criterion of the first round)
+    rmse0: float                  # RMSE of the first fit
+    rmse: float                   # RMSE of the final fit
+    sigma: float                  # per-sample noise std implied by rmse
+    rounds: int                   # fit-and-mask rounds run
+    mask_margin: float            # smallest | |r| - k_mask*RMSE | / RMSE over every round's test
+
+
+def fit_masked_bandpass(B: np.ndarray, nsamps: int, params: "RfiParams") -> BandpassFit:
+    """Bandpass correction of Sec. 2.2.1 on the time-averaged bandpass B[c]
+    of a chunk of nsamps samples: fit a degree-p polynomial, mask the
+    channels whose residual exceeds k_mask times the fit's RMSE, replace them
+    by the mean of their nearest unmasked neighbours and fit again; the round
+    repeats, the mask only growing, until a round masks no new channel or
+    mask_passes rounds have run.  Then the final fit f and its RMSE.
+
+    Reading: the RMSE is turned into a per-sample noise estimate
+    sigma = RMSE*sqrt(T*C/(C-p-1)) (B[c] is a mean of T samples and the fit
+    has p+1 parameters)."""
+    p = int(params.poly_order)
+    B = np.asarray(B, dtype=np.float64)
+    C, T = B.shape[0], int(nsamps)
+    masked = np.zeros(C, dtype=bool)
+    Bi = B
+    r0, rmse0 = None, None
+    rounds = 0
+    margin = math.inf
+    for _ in range(max(int(params.mask_passes), 1)):
+        rounds += 1
+        fit_i, rmse_i = fit_bandpass(Bi, p)
+        r_i = B - fit_i
+        if r0 is None:
+            r0, rmse0 = r_i, rmse_i
+        if rmse_i > 0:
+            margin = min(margin, float(np.min(np.abs(np.abs(r_i) - params.k_mask * rmse_i)) / rmse_i))
+        grown = masked | (np.abs(r_i) > params.k_mask * rmse_i)
+        settled = bool(np.array_equal(grown, masked))
+        masked = grown
+        Bi = interpolate_masked(B, masked)
+        if settled:
+            break
+    f, rmse = fit_bandpass(Bi, p)
+    sigma = rmse * math.sqrt(T * C / (C - p - 1))
+    return BandpassFit(masked=masked, bandpass_interp=Bi, fit=f, residual0=r0, rmse0=rmse0,
+                       rmse=rmse, sigma=sigma, rounds=rounds, mask_margin=margin)
+
+
 def chunk_bounds(T: int, W: int):
     """Non-overlapping windows of width W along time; the last may be short."""
     J = (T + W - 1) // W
@@ -191,13 +246,9 @@ def chunk_bounds(T: int, W: int):
 def rfi_clean(x: np.ndarray, params: RfiParams = RfiParams()) -> RfiResult:
     """The three-stage thresholding pass of Sec. 2.2.1 on one chunk x[C][T].
 
-    1. Bandpass correction: B[c] = time average of channel c.  Fit a degree-p
-       polynomial; channels whose residual exceeds k_mask*RMSE0 are masked and
-       replaced by the mean of their nearest unmasked neighbours; refit -> f[c]
-       and RMSE.  With mask_passes > 1 the fit-and-mask round repeats on the
-       interpolated bandpass, the mask only growing, before the final fit.  Reading: the RMSE is turned into a per-sample noise estimate
-       sigma = RMSE*sqrt(T*C/(C-p-1)) (B[c] is a mean of T samples and the fit
-       has p+1 parameters), and f is subtracted from every spectrum.
+    1. Bandpass correction: B[c] = time average of channel c, then the
+       masked polynomial fit of ``fit_masked_bandpass`` -> f[c], RMSE and the
+       per-sample noise estimate sigma; f is subtracted from every spectrum.
     2. Channel thresholding: partition each channel into chunks of W_c; a chunk
        whose mean |m| exceeds k_chan*sigma/sqrt(L_j) is flagged together with
        its time-adjacent chunks j-1, j+1 of the same channel.  Flagged samples
@@ -218,18 +269,9 @@ def rfi_clean(x: np.ndarray, params: RfiParams = RfiParams()) -> RfiResult:
 
     # 1. Bandpass correction
     B = x64.sum(axis=1) / T
-    masked = np.zeros(C, dtype=bool)
-    Bi = B
-    r0, rmse0 = None, None
-    for _ in range(max(int(params.mask_passes), 1)):
-        fit_i, rmse_i = fit_bandpass(Bi, p)
-        r_i = B - fit_i
-        if r0 is None:
-            r0, rmse0 = r_i, rmse_i
-        masked = masked | (np.abs(r_i) > params.k_mask * rmse_i)
-        Bi = interpolate_masked(B, masked)
-    f, rmse = fit_bandpass(Bi, p)
-    sigma = rmse * math.sqrt(T * C / (C - p - 1))
+    bp = fit_masked_bandpass(B, T, params)
+    masked, Bi, f, r0 = bp.masked, bp.bandpass_interp, bp.fit, bp.residual0
+    rmse0, rmse, sigma = bp.rmse0, bp.rmse, bp.sigma
     y = x64 - f[:, None]
 
     # 2. Channel thresholding
@@ -255,9 +297,8 @@ def rfi_clean(x: np.ndarray, params: RfiParams = RfiParams()) -> RfiResult:
     ties = {}
     eps = 1e-9
     if rmse0 > 0:
-        dm_ = np.abs(np.abs(r0) - params.k_mask * rmse0) / rmse0
-        ties["mask_min"] = float(dm_.min())
-        ties["mask_count"] = int((dm_ < eps).sum())
+        ties["mask_min"] = bp.mask_margin
+        ties["mask_count"] = int(bp.mask_margin < eps)
     if sigma > 0:
         unit_c = sigma / np.sqrt(lens.astype(np.float64))
         dc = np.abs(np.abs(m) - thr_chan[None, :]) / unit_c[None, :]
@@ -638,6 +679,86 @@ def cluster(sample, dm_index, snr, t_eps: int, dm_eps: int, snr_eps: float, min_
             if cn.shape[0]:
                 labels[p] = rank[comp[cn[0]]]
     return labels, len(first)
+
+
+def fdbscan(sample, dm_index, snr, t_eps: int, dm_eps: int, snr_eps: float, min_pts: int):
+    """FDBSCAN labels of the detections (Sec. 2.3): DBSCAN whose cluster
+    expansion issues region queries only from a few representative points of
+    each core point's neighbourhood.  Sequential, in the paper's terms:
+
+    1. visit the points in index order; an unclassified point whose
+       neighbourhood (the same Eps-neighbourhood as ``cluster``) holds fewer
+       than min_pts points is marked noise;
+    2. an unclassified core point starts a new cluster: every point of its
+       neighbourhood that is unclassified or noise joins it;
+    3. the representatives of that neighbourhood become seeds: with the core
+       point at the origin, for each dimension (sample, DM index, SNR) and
+       each direction, the member lying farthest in that direction, i.e. two
+       per dimension;
+    4. each seed is region-queried; if it is a core point, its unclassified
+       or noise neighbours join the cluster and its own representatives
+       become seeds; the cluster is complete when no seed is left.
+
+    Readings: a direction in which no member lies off the origin has no
+    representative; of several members equally far the lowest-indexed one is
+    taken (SNR offsets in FP32, the stored precision); a point is
+    region-queried at most once, so a seed already queried (in this cluster
+    or an earlier one, or by step 1) is not expanded again; a point another
+    cluster has taken keeps its cluster.  A point density-reachable only
+    through a core point that is never a representative is lost (noise) or
+    starts a cluster of its own later (a split).
+
+    Returns (labels int32, -1 for noise; number of clusters; number of
+    region queries)."""
+    sample = np.asarray(sample, np.int64)
+    dm = np.asarray(dm_index, np.int64)
+    q32 = np.asarray(snr, np.float32)
+    nb = cluster_neighbours(sample, dm, q32, t_eps, dm_eps, snr_eps)
+    n = len(nb)
+    UNCLASSIFIED, NOISE = -2, -1
+    labels = np.full(n, UNCLASSIFIED, np.int64)
+    queried = np.zeros(n, dtype=bool)
+
+    def representatives(p, members):
+        reps = []
+        for offs in (sample[members] - sample[p], dm[members] - dm[p], q32[members] - q32[p]):
+            for sign in (1, -1):
+                v = offs * sign
+                far = v.max()
+                if far > 0:
+                    reps.append(int(members[np.flatnonzero(v == far)[0]]))
+        return reps
+
+    def join(members, cid):
+        free = (labels[members] == UNCLASSIFIED) | (labels[members] == NOISE)
+        labels[members[free]] = cid
+
+    nclusters = 0
+    nqueries = 0
+    for p in range(n):
+        if labels[p] != UNCLASSIFIED:
+            continue
+        queried[p] = True
+        nqueries += 1
+        if nb[p].shape[0] < int(min_pts):
+            labels[p] = NOISE
+            continue
+        cid = nclusters
+        nclusters += 1
+        join(nb[p], cid)
+        seeds = collections.deque(representatives(p, nb[p]))
+        while seeds:
+            s = seeds.popleft()
+            if queried[s]:
+                continue
+            queried[s] = True
+            nqueries += 1
+            if nb[s].shape[0] < int(min_pts):
+                continue
+            join(nb[s], cid)
+            seeds.extend(representatives(s, nb[s]))
+    labels[labels == UNCLASSIFIED] = NOISE
+    return labels.astype(np.int32), nclusters, nqueries
 
 
 CLUSTER_INFO_DTYPE = np.dtype([("peak_dm_index", np.int32), ("npoints", np.int32), ("ndm_rows", np.int32),
