@@ -66,7 +66,8 @@ typedef struct {
   double k_mask;        /* channel masking factor x RMSE of the fit [5]      */
   double k_chan;        /* chunk-mean threshold in noise stds [5]            */
   double k_spec;        /* spectrum-mean threshold in noise stds [5]         */
-  int32_t mask_passes;  /* fit-and-mask rounds before the final fit [1]      */
+  int32_t mask_passes;  /* most fit-and-mask rounds, 1..16 [8]; rounds stop
+                           early once one masks no new channel              */
   int32_t reserved;     /* must be 0                                         */
 } mb_rfi_params;
 
@@ -194,7 +195,12 @@ mb_status rfi_state_layout(const mb_plan* plan, int64_t nsamps, mb_rfi_layout* l
  * (plan's in_dtype, [C][nsamps] with leading dimension ld): per-channel and per-chunk sums and per-sample
  * spectrum sums in one HBM pass (FP64 accumulation), the bandpass fit with
  * channel masking on one workgroup, chunk flags with extension to the
- * adjacent chunks, and spectrum flags.  The input is not modified; the
+ * adjacent chunks, and spectrum flags.  Masking: the time-averaged bandpass
+ * is fitted, channels whose residual exceeds k_mask times the fit's RMSE are
+ * masked (replaced by the mean of their nearest unmasked neighbours) and the
+ * round repeats on the interpolated bandpass until a round masks no new
+ * channel or mask_passes rounds have run (a bright channel can hide a fainter
+ * one in the first RMSE); the last fit is the bandpass the pass subtracts.  The input is not modified; the
  * cleaning is applied on the fly by dedisp_execute.  d_state must be at
  * least layout.total_bytes and 256-byte aligned; its previous contents are
  * overwritten.  Errors: MB_EINVAL (shape, params, small state buffer). */
@@ -407,9 +413,23 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
  * bytes on the plan's device. */
 mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out);
 mb_status dedisp_beam_destroy(mb_beam* beam);
-/* Forgets the stream history (the next chunk is the first).  Waits for the
- * device to be idle. */
+/* Forgets the stream history (the next chunk is the first, starting at
+ * absolute sample 0).  Waits for the device to be idle. */
 mb_status dedisp_beam_reset(mb_beam* beam);
+/* Forgets the stream history without waiting: the next chunk is the first
+ * of a stream whose first sample has absolute index `position` (0..2^62), so
+ * after a gap in the input (dropped chunks, Sec. 3's soft-real-time policy)
+ * outputs and detections keep absolute sample indices.  The device-side
+ * position is written by a kernel enqueued on `stream`; the host-side count
+ * changes at once, so the next chunk must be enqueued after this call, on
+ * the same stream or one ordered after it.  Errors: MB_EINVAL. */
+mb_status dedisp_beam_seek(mb_beam* beam, int64_t position, void* stream);
+/* Device address of an int64 that every execute of a chunk on this beam
+ * sets, in stream order, to the absolute index of the chunk's first output
+ * (mb_exec_info.sample0).  Passed to detect_candidates as d_sample0, it keeps
+ * the triplets of a captured chunk step on the right samples at every replay.
+ * The address is valid until the beam is destroyed. */
+mb_status dedisp_beam_sample0_ptr(const mb_beam* beam, const int64_t** d_sample0);
 /* Advances the host-side sample count by nsamps without launching anything:
  * for chunks enqueued by replaying a captured graph. */
 mb_status dedisp_beam_advance(mb_beam* beam, int64_t nsamps);
@@ -422,7 +442,9 @@ mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes);
 
 /* Thresholds z = (D[d][t] - a_d - b_d*t) / sigma_d > nsigma (strict, FP64)
  * over d_out [ndms][ld_out], t < nout, with d_norm from dedisp_execute.
- * Writes candidates in (dm_index, sample) order, sample = sample0 + t:
+ * Writes candidates in (dm_index, sample) order, sample = s0 + t, where s0 is
+ * sample0 plus, when d_sample0 (device int64, nullable) is given, the value it
+ * holds when the kernels run (dedisp_beam_sample0_ptr):
  * the first min(count, capacity) to d_cands, the true count to *d_count
  * (device int64).  More than capacity is not an error at enqueue time: the
  * caller compares *d_count with capacity once the stream has run.
@@ -430,7 +452,7 @@ mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes);
  * sample.  d_work: at least detect_workspace_size bytes, 256-byte aligned. */
 mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nout,
                             int64_t ld_out, const mb_norm* d_norm, int64_t sample0,
-                            double nsigma, mb_candidate* d_cands, int64_t capacity,
+                            const int64_t* d_sample0, double nsigma, mb_candidate* d_cands, int64_t capacity,
                             int64_t* d_count, mb_peak* d_peaks, void* d_work,
                             size_t work_bytes, void* stream);
 

@@ -99,8 +99,10 @@ _SIGS = {
     "dedisp_execute_batch": ([ctypes.POINTER(BatchItem), c_i32, c_vp, c_sz, ctypes.POINTER(ExecInfo),
                               c_vp], c_i32),
     "dedisp_beam_position": ([c_vp, ctypes.POINTER(c_i64)], c_i32),
+    "dedisp_beam_seek": ([c_vp, c_i64, c_vp], c_i32),
+    "dedisp_beam_sample0_ptr": ([c_vp, ctypes.POINTER(c_vp)], c_i32),
     "detect_workspace_size": ([c_vp, ctypes.POINTER(c_sz)], c_i32),
-    "detect_candidates": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_vp,
+    "detect_candidates": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_dbl, c_vp, c_i64, c_vp, c_vp,
                            c_vp, c_sz, c_vp], c_i32),
     "mb_status_str": ([c_i32], ctypes.c_char_p),
     "mb_last_error": ([], ctypes.c_char_p),

@@ -30,7 +30,7 @@ class RfiConfig:
     k_mask: float = 5.0
     k_chan: float = 5.0
     k_spec: float = 5.0
-    mask_passes: int = 1
+    mask_passes: int = 8
 
     def to_c(self) -> L.RfiParams:
         return L.RfiParams(self.poly_order, self.window, self.k_mask, self.k_chan, self.k_spec,
@@ -211,12 +211,18 @@ class Plan:
         return cands, count, peaks, work
 
     def detect(self, out: torch.Tensor, nout: int, norm: torch.Tensor, nsigma: float,
-               sample0: int = 0, capacity: int = 1 << 16, buffers=None, stream=None):
-        """Enqueues detection; returns the device buffers (cands, count, peaks, work)."""
+               sample0: int = 0, capacity: int = 1 << 16, buffers=None, stream=None,
+               beam: "Beam | None" = None):
+        """Enqueues detection; returns the device buffers (cands, count, peaks, work).
+
+        With a beam, the absolute index of the first output is read on the
+        device when the kernels run (the value the beam's last execute stored),
+        plus sample0: a captured step then labels every replay's samples."""
         cands, count, peaks, work = buffers if buffers is not None else self.alloc_detect(capacity)
         cap = cands.numel() // L.CANDIDATE_BYTES
+        d_s0 = ctypes.c_void_p(beam.sample0_ptr()) if beam is not None else None
         L.check(L.lib().detect_candidates(self._h, _ptr(out), int(nout), out.stride(0), _ptr(norm),
-                                          int(sample0), float(nsigma), _ptr(cands), cap, _ptr(count),
+                                          int(sample0), d_s0, float(nsigma), _ptr(cands), cap, _ptr(count),
                                           _ptr(peaks), _ptr(work), work.numel(), _stream_ptr(stream)),
                 "detect_candidates")
         return cands, count, peaks, work
@@ -456,6 +462,18 @@ class Beam:
     def reset(self):
         L.check(L.lib().dedisp_beam_reset(self._h), "dedisp_beam_reset")
 
+    def seek(self, position: int, stream=None):
+        """Restarts the stream at absolute sample `position` (enqueued on the
+        stream; the ring is forgotten)."""
+        L.check(L.lib().dedisp_beam_seek(self._h, int(position), _stream_ptr(stream)), "dedisp_beam_seek")
+
+    def sample0_ptr(self) -> int:
+        """Device address of the int64 holding the absolute index of the
+        last executed chunk's first output."""
+        p = ctypes.c_void_p()
+        L.check(L.lib().dedisp_beam_sample0_ptr(self._h, ctypes.byref(p)), "dedisp_beam_sample0_ptr")
+        return p.value
+
     def advance(self, nsamps: int):
         """Host-side bookkeeping for chunks enqueued by a graph replay."""
         L.check(L.lib().dedisp_beam_advance(self._h, int(nsamps)), "dedisp_beam_advance")
@@ -516,7 +534,11 @@ class ChunkGraph:
         _, _, nout, s0 = p.execute(self.x, rfi_state=self.state, out=self.out, norm=self.norm,
                                    beam=self.beam)
         assert nout == self.nout
-        p.detect(self.out, nout, self.norm, self.nsigma, sample0=s0, buffers=self.det)
+        if self.beam is not None:
+            # the absolute sample is read on the device at every replay
+            p.detect(self.out, nout, self.norm, self.nsigma, buffers=self.det, beam=self.beam)
+        else:
+            p.detect(self.out, nout, self.norm, self.nsigma, sample0=s0, buffers=self.det)
         self.sample0 = s0
 
     def replay(self):
@@ -574,8 +596,9 @@ class BatchGraph:
                                              self.norms, self.beams)]
         res = execute_batch(jobs, work=self.work)
         s0s = []
-        for p, (out, norm, nout, s0), det in zip(self.plans, res, self.dets):
-            p.detect(out, nout, norm, self.nsigma, sample0=s0, buffers=det)
+        for p, (out, norm, nout, s0), det, b in zip(self.plans, res, self.dets, self.beams):
+            # the absolute sample is read on the device at every replay
+            p.detect(out, nout, norm, self.nsigma, buffers=det, beam=b)
             s0s.append(s0)
         self.sample0 = s0s
 

@@ -898,8 +898,22 @@ __global__ __launch_bounds__(64 * NW) void dedisp_batch_kernel(BatchArgs B) {
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
-// Advances a beam's device-side sample count after a chunk.
-__global__ void beam_advance_kernel(int64_t* seen, int64_t L) { *seen += L; }
+// Device-side stream position of a beam: st[0] samples seen since the stream
+// (re)started, st[1] absolute index of the last chunk's first output, st[2]
+// absolute index of the stream's first sample.  After a chunk of L samples
+// the first output is max(0, seen - s_max) samples into the stream.
+__global__ void beam_advance_kernel(int64_t* st, int64_t L, int64_t smax) {
+  const int64_t seen = st[0];
+  st[1] = st[2] + (seen > smax ? seen - smax : 0);
+  st[0] = seen + L;
+}
+
+// Restarts a beam's stream at absolute sample `base` (the ring is forgotten).
+__global__ void beam_seek_kernel(int64_t* st, int64_t base) {
+  st[0] = 0;
+  st[1] = base;
+  st[2] = base;
+}
 
 // Per-(DM, channel) window offset inside the channel's staged region, with
 // p = s[d][c] - (s[d0][c] & ~3).  Four copies: the window starts at position
@@ -1025,7 +1039,7 @@ hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, cons
 
 hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, int64_t L, int32_t C,
                               const CleanView& cv, const float* fit32, float* ring, int64_t R,
-                              int64_t* seen_dev, hipStream_t s) {
+                              int64_t* seen_dev, int64_t smax, hipStream_t s) {
   const int64_t n = L < R ? L : R;
   if (n > 0) {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)C);
@@ -1041,7 +1055,12 @@ hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, 
     }
 #undef MBTP_R
   }
-  hipLaunchKernelGGL(beam_advance_kernel, dim3(1), dim3(1), 0, s, seen_dev, L);
+  hipLaunchKernelGGL(beam_advance_kernel, dim3(1), dim3(1), 0, s, seen_dev, L, smax);
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_seek(int64_t* seen_dev, int64_t base, hipStream_t s) {
+  hipLaunchKernelGGL(beam_seek_kernel, dim3(1), dim3(1), 0, s, seen_dev, base);
   return hipGetLastError();
 }
 

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(1024) void detect_count_kernel(const float* __restr
                                                             int64_t ld_out, int64_t nout,
                                                             const NormDev* __restrict__ norm,
                                                             double nsigma, int64_t sample0,
+                                                            const int64_t* __restrict__ d_sample0,
                                                             int64_t* __restrict__ counts,
                                                             PeakDev* __restrict__ peaks) {
   __shared__ double shr[kDetectSegs];
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(1024) void detect_count_kernel(const float* __restr
   }
   __syncthreads();
   if (threadIdx.x == 0 && peaks) {
+    if (d_sample0) sample0 += *d_sample0;
     PeakDev p;
     p.reserved = 0;
     if (n.degenerate || nout == 0) {
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(1024) void detect_write_kernel(const float* __restr
                                                             int64_t ld_out, int64_t nout,
                                                             const NormDev* __restrict__ norm,
                                                             double nsigma, int64_t sample0,
+                                                            const int64_t* __restrict__ d_sample0,
                                                             double dm_start, double dm_step,
                                                             const int64_t* __restrict__ counts,
                                                             const int64_t* __restrict__ offsets,
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(1024) void detect_write_kernel(const float* __restr
   if (counts[slot] == 0) return;
   int64_t pos = offsets[slot];
   if (pos >= capacity) return;
+  if (d_sample0) sample0 += *d_sample0;
   const float* row = out + (int64_t)d * ld_out;
   const NormDev n = norm[d];
   const double thr = nsigma * n.sigma;
@@ -313,17 +317,17 @@ hipError_t launch_norm(const float* out, int64_t ld_out, int64_t nout, int32_t n
 }
 
 hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
-                         const NormDev* norm, int64_t sample0, double nsigma, double dm_start,
-                         double dm_step, CandDev* cands, int64_t capacity, int64_t* d_count,
+                         const NormDev* norm, int64_t sample0, const int64_t* d_sample0, double nsigma,
+                         double dm_start, double dm_step, CandDev* cands, int64_t capacity, int64_t* d_count,
                          PeakDev* peaks, void* work, hipStream_t s) {
   int64_t* counts = static_cast<int64_t*>(work);
   int64_t* offsets = counts + kDetectSegs * (int64_t)ndms;
   hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout,
-                     norm, nsigma, sample0, counts, peaks);
+                     norm, nsigma, sample0, d_sample0, counts, peaks);
   hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(1024), 0, s, counts,
                      kDetectSegs * (int64_t)ndms, offsets, d_count);
   hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout,
-                     norm, nsigma, sample0, dm_start, dm_step, counts, offsets, cands, capacity);
+                     norm, nsigma, sample0, d_sample0, dm_start, dm_step, counts, offsets, cands, capacity);
   return hipGetLastError();
 }
 

@@ -186,10 +186,14 @@ hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs
 hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]);
 
 // Writes the chunk's last min(L, R) cleaned samples into the ring at the
-// positions given by the beam's device-side sample count, then advances it.
+// positions given by the beam's device-side sample count, then advances the
+// beam's device-side position (seen_dev: [seen, first output of the chunk,
+// stream base], see beam_advance_kernel).
 hipError_t launch_ring_update(int dtype, bool clean, const void* x, int64_t ld, int64_t L,
                               int32_t C, const CleanView& cv, const float* fit32, float* ring,
-                              int64_t R, int64_t* seen_dev, hipStream_t s);
+                              int64_t R, int64_t* seen_dev, int64_t smax, hipStream_t s);
+// Restarts a beam's device-side position at absolute sample `base`.
+hipError_t launch_beam_seek(int64_t* seen_dev, int64_t base, hipStream_t s);
 
 struct NormDev { double a, b, sigma; int32_t degenerate, reserved; };
 struct CandDev { int32_t dm_index, reserved; int64_t sample; float snr, dm; };
@@ -230,7 +234,7 @@ hipError_t launch_mulaw_decode_complex(const uint8_t* codes, int64_t ld_codes, c
                                        int64_t ncols, float mu, float* out, int64_t ld_out, hipStream_t s);
 
 hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
-                         const NormDev* norm, int64_t sample0, double nsigma,
+                         const NormDev* norm, int64_t sample0, const int64_t* d_sample0, double nsigma,
                          double dm_start, double dm_step, CandDev* cands, int64_t capacity,
                          int64_t* d_count, PeakDev* peaks, void* work, hipStream_t s);
 

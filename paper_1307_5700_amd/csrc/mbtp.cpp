@@ -102,9 +102,13 @@ struct mb_plan {
 struct mb_beam {
   const mb_plan* plan = nullptr;
   float* d_ring = nullptr;
-  int64_t* d_seen = nullptr;   // device-side sample count: the ring position kernels read
+  // device-side position: [0] samples seen since the stream (re)started (the
+  // ring position kernels read), [1] absolute index of the last chunk's first
+  // output, [2] absolute index of the stream's first sample
+  int64_t* d_seen = nullptr;
   int64_t R = 0;
-  int64_t seen = 0;
+  int64_t seen = 0;            // host copy of [0]
+  int64_t base = 0;            // host copy of [2]
 };
 
 namespace {
@@ -234,7 +238,7 @@ void mb_rfi_defaults(mb_rfi_params* p) {
   p->k_mask = 5.0;
   p->k_chan = 5.0;
   p->k_spec = 5.0;
-  p->mask_passes = 1;
+  p->mask_passes = 8;
   p->reserved = 0;
 }
 
@@ -398,9 +402,9 @@ mb_status dedisp_beam_create(const mb_plan* plan, mb_beam** out) {
       return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
   }
-  const int64_t zero = 0;
-  if (hipMalloc(&b->d_seen, sizeof(int64_t)) != hipSuccess ||
-      hipMemcpy(b->d_seen, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+  const int64_t zero[3] = {0, 0, 0};
+  if (hipMalloc(&b->d_seen, sizeof(zero)) != hipSuccess ||
+      hipMemcpy(b->d_seen, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(b->d_ring);
     (void)hipFree(b->d_seen);
     delete b;
@@ -420,10 +424,26 @@ mb_status dedisp_beam_destroy(mb_beam* beam) {
 
 mb_status dedisp_beam_reset(mb_beam* beam) {
   if (!beam) return fail(MB_EINVAL, "beam is NULL");
-  const int64_t zero = 0;
+  const int64_t zero[3] = {0, 0, 0};
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(beam->d_seen, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(beam->d_seen, zero, sizeof(zero), hipMemcpyHostToDevice));
   beam->seen = 0;
+  beam->base = 0;
+  return ok();
+}
+
+mb_status dedisp_beam_seek(mb_beam* beam, int64_t position, void* stream) {
+  if (!beam) return fail(MB_EINVAL, "beam is NULL");
+  if (position < 0 || position > (int64_t(1) << 62)) return fail(MB_EINVAL, "position must be in [0, 2^62]");
+  HIP_TRY(launch_beam_seek(beam->d_seen, position, static_cast<hipStream_t>(stream)));
+  beam->seen = 0;
+  beam->base = position;
+  return ok();
+}
+
+mb_status dedisp_beam_sample0_ptr(const mb_beam* beam, const int64_t** d_sample0) {
+  if (!beam || !d_sample0) return fail(MB_EINVAL, "beam and d_sample0 must not be NULL");
+  *d_sample0 = beam->d_seen + 1;
   return ok();
 }
 
@@ -484,6 +504,8 @@ mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t 
       return fail(MB_EINVAL, "ld_out (%lld) must be >= nout (%lld) and a multiple of 4", (long long)ld_out, (long long)nout_c);
   }
   if (d_norm && !check_aligned(d_norm, 8)) return fail(MB_EINVAL, "norm must be 8-byte aligned");
+  if (beam && beam->base + seen > (int64_t(1) << 62) - nsamps)
+    return fail(MB_EINVAL, "absolute sample index of the stream would exceed 2^62");
   P = Prepared{};
   P.plan = plan;
   P.beam = beam;
@@ -495,7 +517,7 @@ mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t 
   P.ld_out = ld_out;
   P.d_norm = d_norm;
   P.nout = nout_c;
-  P.sample0 = seen - veff;
+  P.sample0 = (beam ? beam->base : 0) + seen - veff;
   if (P.clean) {
     const RfiGeom g = rfi_geometry(plan->desc.nchans, nsamps, plan->desc.rfi.window);
     const char* stp = static_cast<const char*>(d_rfi_state);
@@ -543,7 +565,7 @@ mb_status finish_item(Prepared& P, hipStream_t s) {
     HIP_TRY(launch_norm(P.d_out, P.ld_out, P.nout, plan->desc.ndms, reinterpret_cast<NormDev*>(P.d_norm), s));
   if (P.beam) {
     HIP_TRY(launch_ring_update(plan->desc.in_dtype, P.clean, P.d_in, P.ld, P.nsamps, plan->desc.nchans,
-                               P.cv, P.fit32, P.beam->d_ring, P.beam->R, P.beam->d_seen, s));
+                               P.cv, P.fit32, P.beam->d_ring, P.beam->R, P.beam->d_seen, plan->smax, s));
     P.beam->seen += P.nsamps;
   }
   return MB_OK;
@@ -848,8 +870,8 @@ mb_status detect_workspace_size(const mb_plan* plan, size_t* bytes) {
 }
 
 mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nout, int64_t ld_out,
-                            const mb_norm* d_norm, int64_t sample0, double nsigma,
-                            mb_candidate* d_cands, int64_t capacity, int64_t* d_count,
+                            const mb_norm* d_norm, int64_t sample0, const int64_t* d_sample0,
+                            double nsigma, mb_candidate* d_cands, int64_t capacity, int64_t* d_count,
                             mb_peak* d_peaks, void* d_work, size_t work_bytes, void* stream) {
   if (!plan) return fail(MB_EINVAL, "plan is NULL");
   if (nout < 0 || sample0 < 0) return fail(MB_EINVAL, "nout and sample0 must be >= 0");
@@ -862,7 +884,7 @@ mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nou
   if (!d_work || work_bytes < need || !check_aligned(d_work, 256))
     return fail(MB_EINVAL, "workspace must be 256-byte aligned with at least %zu bytes", need);
   HIP_TRY(launch_detect(d_out, ld_out, nout, plan->desc.ndms, reinterpret_cast<const NormDev*>(d_norm),
-                        sample0, nsigma, plan->desc.dm_start, plan->desc.dm_step,
+                        sample0, d_sample0, nsigma, plan->desc.dm_start, plan->desc.dm_step,
                         reinterpret_cast<CandDev*>(d_cands), capacity, d_count,
                         reinterpret_cast<PeakDev*>(d_peaks), d_work, static_cast<hipStream_t>(stream)));
   return ok();

@@ -295,19 +295,29 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
   gram_cholesky<D>(C, sh, L);   // (its barriers also publish binterp/masked)
   double rmse0 = 0.0;
   int any_left = 1;
+  // Fit-and-mask rounds: each fits the interpolated bandpass and masks the
+  // channels whose raw residual exceeds k_mask times that fit's RMSE (the
+  // mask only grows).  They stop after a round that masks no new channel,
+  // whose fit is then already the final one, or after mask_passes rounds.
   const int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
+  bool settled = false;
+  double rmse = 0.0;
   for (int pass = 0; pass < passes; ++pass) {
     const double rmse_i = fit_poly<D>(binterp, C, L, fit, sh, coef_sh);
     if (pass == 0) rmse0 = rmse_i;
+    rmse = rmse_i;
     const double thr = prm.k_mask * rmse_i;
-    int left = 0;
+    int bits = 0;                            // bit 0: an unmasked channel is left; bit 1: the mask grew
     for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
       const double r = bsum[c] * invT - fit[c];
-      if (fabs(r) > thr) masked[c] = 1;
-      left |= masked[c] ? 0 : 1;
+      if (fabs(r) > thr && !masked[c]) { masked[c] = 1; bits |= 2; }
+      bits |= masked[c] ? 0 : 1;
     }
-    any_left = __syncthreads_or(left);       // also publishes masked[]
+    // the block-wide ORs also publish masked[]
+    const int all = __syncthreads_or(bits & 1) | (__syncthreads_or(bits & 2) ? 2 : 0);
+    any_left = all & 1;
     if (!any_left) break;
+    if (!(all & 2)) { settled = true; break; }
     // nearest unmasked neighbour on each side (one side at a band edge)
     for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
       if (!masked[c]) { binterp[c] = bsum[c] * invT; continue; }
@@ -335,7 +345,7 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
     }
     return;
   }
-  const double rmse = fit_poly<D>(binterp, C, L, fit, sh, coef_sh);
+  if (!settled) rmse = fit_poly<D>(binterp, C, L, fit, sh, coef_sh);
   double sums[2] = {0.0, 0.0};
   for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
     fit32[c] = (float)fit[c];

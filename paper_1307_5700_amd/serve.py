@@ -11,6 +11,15 @@ streams.  A beam has at most one chunk on the device at a time (its ring is
 sequential).  Each chunk's latency runs from its arrival to the moment its
 candidates are on the host.
 
+Soft real time (Sec. 3): when the pipeline falls behind, the buffering stage
+drops data until the pipeline advances instead of letting the backlog grow.
+With a backlog bound, a chunk that arrives while its beam already has that
+many chunks waiting is dropped (or, with drop="oldest", the oldest waiting
+chunk makes room for it) and counted.  Every chunk keeps its absolute sample
+position, so the first chunk after a gap restarts the beam's stream there
+(its overlap ring is forgotten) and outputs and detections keep absolute
+sample indices across the gap.
+
 Every result equals what the beam gets when served alone: all kernels are
 deterministic and a beam's state is its own.
 """
@@ -66,6 +75,8 @@ class Request:
     data: "np.ndarray | torch.Tensor"  # host chunk [C][L]: numpy, or a pinned CPU tensor
                                        # (copied to the device directly, no staging copy)
     t_arrival: float
+    sample_start: int | None = None    # absolute index of the chunk's first sample
+                                       # (None: right after the beam's previous chunk)
     seq: int = 0
     t_done: float = 0.0
     nout: int = 0
@@ -100,8 +111,14 @@ class Server:
     """Continuous-batching server for beams that share one plan shape."""
 
     def __init__(self, plan: A.Plan, max_chunk: int, hbm_budget: int, nsigma: float = 6.0,
-                 capacity: int = 1 << 15, max_slots: int = 16, nstreams: int = 4, rfi: bool = True):
+                 capacity: int = 1 << 15, max_slots: int = 16, nstreams: int = 4, rfi: bool = True,
+                 max_backlog: int | None = None, drop: str = "arrival"):
+        if max_backlog is not None and max_backlog < 1:
+            raise ValueError("max_backlog must be >= 1 (or None for no bound)")
+        if drop not in ("arrival", "oldest"):
+            raise ValueError("drop must be 'arrival' or 'oldest'")
         self.plan, self.max_chunk, self.nsigma, self.rfi = plan, max_chunk, nsigma, rfi
+        self.max_backlog, self.drop = max_backlog, drop
         self.capacity = capacity
         ring = footprint_bytes(plan, max_chunk)["ring"]
         probe = _Slot(plan, max_chunk, capacity)
@@ -122,6 +139,9 @@ class Server:
         self.in_flight: set = set()
         self.inflight_groups: list = []
         self.done: list = []
+        self.dropped: list = []                  # requests discarded by the backlog bound
+        self.arrived_end: dict[int, int] = {}   # absolute end of each beam's last submitted chunk
+        self.stream_end: dict[int, int] = {}    # absolute end of each beam's last dispatched chunk
         self.lock = threading.Lock()
         self.stats = collections.Counter()
 
@@ -150,15 +170,32 @@ class Server:
                 b = self.waiting_beams.popleft()
                 self.beams[b] = A.Beam(self.plan)
 
-    def submit(self, req: Request):
+    def submit(self, req: Request) -> bool:
+        """Queues a chunk; returns False when the backlog bound dropped it."""
         if req.data.shape[0] != self.plan.nchans or req.data.shape[1] > self.max_chunk:
             raise ValueError("chunk does not fit the server's plan or maximum chunk length")
         if req.data.shape[1] % 4:
             raise ValueError("chunk lengths must be multiples of 4 samples")
         with self.lock:
-            q = self.queues.setdefault(req.beam_id, collections.deque())
-            req.seq = len(q) + self.stats[("seq", req.beam_id)]
+            bid = req.beam_id
+            end = self.arrived_end.get(bid, 0)
+            if req.sample_start is None:
+                req.sample_start = end
+            elif req.sample_start < end:
+                raise ValueError("a beam's chunks must arrive in stream order")
+            self.arrived_end[bid] = req.sample_start + req.data.shape[1]
+            q = self.queues.setdefault(bid, collections.deque())
+            req.seq = self.stats[("submitted", bid)]
+            self.stats[("submitted", bid)] += 1
+            if self.max_backlog is not None and len(q) >= self.max_backlog:
+                victim = req if self.drop == "arrival" else q.popleft()
+                self.dropped.append(victim)
+                self.stats["dropped"] += 1
+                self.stats[("dropped", bid)] += 1
+                if victim is req:
+                    return False
             q.append(req)
+            return True
 
     # ---- dispatch ----
     def _ready(self, now: float):
@@ -181,7 +218,6 @@ class Server:
             reqs, slots = [], []
             for bid in ready[:n]:
                 reqs.append(self.queues[bid].popleft())
-                self.stats[("seq", bid)] += 1
                 slots.append(self.slots_free.pop())
                 self.in_flight.add(bid)
         self._launch(reqs, slots)
@@ -195,6 +231,13 @@ class Server:
         with torch.cuda.stream(stream):
             jobs = []
             for r, sl in zip(reqs, slots):
+                bm = self.beams[r.beam_id]
+                if r.sample_start != self.stream_end.get(r.beam_id, 0):
+                    # a gap (dropped chunks): the stream restarts at this chunk,
+                    # keeping absolute sample indices
+                    bm.seek(r.sample_start, stream=stream)
+                    self.stats["stream_restarts"] += 1
+                self.stream_end[r.beam_id] = r.sample_start + r.data.shape[1]
                 Lr = r.data.shape[1]
                 n = plan.nchans * Lr
                 x = sl.x[:n].view(plan.nchans, Lr)
@@ -206,8 +249,7 @@ class Server:
                     h.copy_(src)
                     x.copy_(h, non_blocking=True)
                 st = plan.rfi_threshold(x, sl.state, stream=stream) if self.rfi else None
-                jobs.append(dict(plan=plan, x=x, rfi_state=st, out=sl.out, norm=sl.norm,
-                                 beam=self.beams[r.beam_id]))
+                jobs.append(dict(plan=plan, x=x, rfi_state=st, out=sl.out, norm=sl.norm, beam=bm))
             res = A.execute_batch(jobs, work=self.work[si], stream=stream)
             for r, sl, (out, norm, nout, s0) in zip(reqs, slots, res):
                 r.nout, r.sample0 = nout, s0
@@ -294,5 +336,6 @@ def poisson_run(server: Server, chunks_per_beam: dict, tsamp_s: float, speedup: 
     res = latency_stats(server.done)
     res.update(wall_s=wall, dm_trial_samples_per_s=dm_samples / wall, speedup=speedup,
                beams=len(chunks_per_beam), stream_seconds_per_beam=span,
-               launches=server.stats["launches"], chunks=server.stats["chunks"])
+               launches=server.stats["launches"], chunks=server.stats["chunks"],
+               dropped=server.stats["dropped"], stream_restarts=server.stats["stream_restarts"])
     return res

@@ -54,7 +54,7 @@ def test_status_strings_and_defaults():
     assert lib.mb_status_str(L.MB_EINVAL) == b"invalid argument"
     p = L.RfiParams()
     lib.mb_rfi_defaults(ctypes.byref(p))
-    assert (p.poly_order, p.window, p.k_mask, p.k_chan, p.k_spec, p.mask_passes) == (3, 256, 5.0, 5.0, 5.0, 1)
+    assert (p.poly_order, p.window, p.k_mask, p.k_chan, p.k_spec, p.mask_passes) == (3, 256, 5.0, 5.0, 5.0, 8)
 
 
 def _desc(L, **kw):
@@ -94,7 +94,9 @@ def test_null_plan_calls_rejected():
     lib = L.lib()
     assert lib.dedisp_execute(None, None, None, 10, 12, None, None, 12, None, None, None) == L.MB_EINVAL
     assert lib.rfi_threshold(None, None, 10, 12, None, 0, None) == L.MB_EINVAL
-    assert lib.detect_candidates(None, None, 0, 0, None, 0, 6.0, None, 0, None, None, None, 0, None) == L.MB_EINVAL
+    assert lib.detect_candidates(None, None, 0, 0, None, 0, None, 6.0, None, 0, None, None, None, 0, None) == L.MB_EINVAL
+    assert lib.dedisp_beam_seek(None, 0, None) == L.MB_EINVAL
+    assert lib.dedisp_beam_sample0_ptr(None, None) == L.MB_EINVAL
     assert lib.dedisp_plan_destroy(None) == L.MB_OK
 
 

@@ -1,5 +1,6 @@
 """Captured chunk steps (HIP graphs) replay to the same results as eager
-execution, every replay, with eager work between replays."""
+execution and as the oracle's stream, every replay, with eager work between
+replays."""
 import json
 import os
 
@@ -10,7 +11,7 @@ import torch
 import oracle
 from paper_1307_5700_amd import synth
 
-from gpu_util import api, to_dev
+from gpu_util import api, compare_candidates, rfi_params, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +25,21 @@ def _beam(T):
     s = oracle.delay_table(**b.plan_kwargs())
     b.pulses = [synth.Pulse(dm_index=100, t0=12000, width=4, amp=1.0)]
     return b, s
+
+
+def _oracle_stream_candidates(chunks, delays, rfi, nsigma, dms):
+    """Per chunk of a stream: (sample0, candidates, z margin) of the oracle's
+    stream outputs, normalised per chunk and thresholded."""
+    res = []
+    for s0, D in oracle.stream_outputs(chunks, delays, rfi):
+        nr = oracle.normalise(D)
+        c, _, margin = oracle.detect(nr.z, nsigma, s0, dms)
+        res.append((s0, c, margin))
+    return res
+
+
+def _device_candidates(plan, det):
+    return plan.candidates_to_host(det[0], det[1])
 
 
 def test_single_shot_graph_replays_match_eager():
@@ -71,13 +87,21 @@ def test_streaming_graph_replays_match_eager_stream():
     xbuf = torch.zeros((512, T), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     g = A.ChunkGraph(plan, xbuf, rfi=True, beam=graph_beam)
+    ref = _oracle_stream_candidates([x[:, k * T:(k + 1) * T] for k in range(9)], s,
+                                    rfi_params(plan.rfi_config), 6.0,
+                                    oracle.dm_trials(b.ndms, b.dm_start, b.dm_step))
     for k in range(2, 9):
         xbuf.copy_(torch.from_numpy(x[:, k * T:(k + 1) * T]).cuda())
         torch.cuda.synchronize()
         s0 = g.replay()
         torch.cuda.synchronize()
-        assert s0 == eager[k][0], k
+        assert s0 == eager[k][0] == ref[k][0], k
         assert torch.equal(g.out[:, :T], eager[k][1]), k
+        # the triplets carry this replay's absolute samples (read on the device)
+        gc, gn = _device_candidates(plan, g.det)
+        assert gn == len(gc)
+        compare_candidates(gc, ref[k][1], ref[k][2])
+    assert sum(len(r[1]) for r in ref[2:]) > 0
     assert graph_beam.position() == eager_beam.position()
 
 
@@ -128,10 +152,14 @@ def test_batch_graph_replays_match_eager_batches():
     eager_step(gb, 0)                         # fill the graph beams' rings
     eager_step(eb, 0)
     torch.cuda.synchronize()
+    refs = [_oracle_stream_candidates([x[:, k * T:(k + 1) * T] for k in range(6)],
+                                      oracle.delay_table(**b.plan_kwargs()), rfi_params(p.rfi_config), 6.0,
+                                      oracle.dm_trials(b.ndms, b.dm_start, b.dm_step))
+            for b, p, x in zip(beams, plans, xs)]
     for buf, x in zip(bufs, xs):
         buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, T:2 * T])))
     g = A.BatchGraph(plans, bufs, gb, rfi=True, nsigma=6.0)
-    for k in range(1, 5):
+    for k in range(1, 6):
         for buf, x in zip(bufs, xs):          # eager work between replays
             buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, k * T:(k + 1) * T])))
         torch.cuda.synchronize()
@@ -143,4 +171,9 @@ def test_batch_graph_replays_match_eager_batches():
             assert nout == T and s0[i] == rs0, (k, i)
             assert torch.equal(g.outs[i][:, :nout], out[:, :nout]), (k, i)
             assert np.array_equal(A.Plan.norm_to_host(g.norms[i]), A.Plan.norm_to_host(norm)), (k, i)
+            assert s0[i] == refs[i][k][0], (k, i)
+            gc, gn = _device_candidates(plans[i], g.dets[i])
+            assert gn == len(gc)
+            compare_candidates(gc, refs[i][k][1], refs[i][k][2])
         assert [b.position() for b in gb] == [b.position() for b in eb]
+    assert all(sum(len(r[1]) for r in ref[1:]) > 0 for ref in refs)

@@ -108,6 +108,29 @@ def test_plain_beam_with_rfi_and_injected_rfi():
     compare_candidates(g["cands"], r["cands"], r["z_margin"])
 
 
+@pytest.mark.parametrize("passes", [1, 2, 8])
+def test_mask_rounds_match_oracle(passes):
+    """A bright burst hides a fainter one behind the first fit's RMSE: one
+    round masks the bright one only, more rounds both.  Masked set, fit,
+    noise estimate and flags equal the oracle's for each round cap."""
+    A = api()
+    f0, df = synth.band(512)
+    beam = synth.Beam(name="mask", nchans=512, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6, ndms=96,
+                      dm_start=0.0, dm_step=0.2, nsamps=16384, dtype="f32", seed=17,
+                      bursts=[synth.Burst(c0=40, nch=5, t0=100, length=6000, amp=20.0),
+                              synth.Burst(c0=300, nch=5, t0=9000, length=1200, amp=20.0)],
+                      spikes=[synth.Spike(t0=12000, length=2, amp=20.0)], rfi=True)
+    x, s = beam_input(beam)
+    plan = A.Plan.from_beam(beam, rfi=A.RfiConfig(mask_passes=passes))
+    g = run_gpu(plan, to_dev(x), rfi=True, nsigma=6.0)
+    r = oracle.run(x, oracle_plan(beam), rfi_params(plan.rfi_config), 6.0)
+    _check_rfi(g, r)
+    want = set(range(40, 45)) | (set() if passes == 1 else set(range(300, 305)))
+    assert set(np.flatnonzero(g["rfi"]["masked"])) == want
+    assert err_sigma(g["D"], r["D"]) < TOL
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+
+
 def test_paper_beam_full_plane():
     """1024 channels, 65536 samples, 640 DMs, RFI at 20 sigma, 5 sigma
     thresholds: every flag, every dedispersed sample and every candidate."""
@@ -118,6 +141,13 @@ def test_paper_beam_full_plane():
     g = run_gpu(plan, to_dev(x), rfi=True, nsigma=beam.nsigma)
     r = oracle.run(x, oracle_plan(beam), rfi_params(plan.rfi_config), beam.nsigma)
     _check_rfi(g, r)
+    # masking settles on exactly the 15 burst channels (three rounds) and the
+    # noise estimate is the unit noise of the beam
+    burst = set()
+    for b in beam.bursts:
+        burst |= set(range(b.c0, b.c0 + b.nch))
+    assert set(np.flatnonzero(g["rfi"]["masked"])) == burst
+    assert g["report"]["sigma"] == pytest.approx(1.0, rel=0.05)
     assert g["nout"] == 65536 - 6102
     assert err_sigma(g["D"], r["D"]) < TOL
     assert err_noise(g["D"], r["D"]) < TOL

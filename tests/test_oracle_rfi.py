@@ -152,6 +152,79 @@ def test_second_mask_pass_catches_hidden_burst():
     assert r2.chunk_flags[200:205].any() and r2.chunk_flags[30:35].any()
 
 
+def test_mask_rounds_stop_once_settled():
+    """The default masks until a round adds no channel: the two-burst beam
+    settles after its second growth, so the default, three rounds and a cap
+    of 16 give the same fit, while one round leaves the fainter burst in."""
+    beam = _rfi_beam(seed=7)
+    beam.bursts = [synth.Burst(c0=30, nch=5, t0=100, length=6000, amp=20.0),
+                   synth.Burst(c0=200, nch=5, t0=9000, length=1200, amp=20.0)]
+    x = synth.render(beam, None)
+    B = x.astype(np.float64).sum(axis=1) / x.shape[1]
+    fits = {n: oracle.fit_masked_bandpass(B, x.shape[1], oracle.RfiParams(mask_passes=n))
+            for n in (1, 2, 3, 16)}
+    default = oracle.fit_masked_bandpass(B, x.shape[1], oracle.RfiParams())
+    assert oracle.RfiParams().mask_passes == 8
+    assert fits[1].rounds == 1 and set(np.flatnonzero(fits[1].masked)) == set(range(30, 35))
+    assert fits[2].rounds == 2 and fits[3].rounds == 3 and fits[16].rounds == 3 and default.rounds == 3
+    for f in (fits[3], fits[16], default):
+        assert np.array_equal(f.masked, fits[2].masked)
+        np.testing.assert_array_equal(f.fit, fits[2].fit)
+        assert f.sigma == fits[2].sigma
+    # the full pass uses the same fit
+    r = oracle.rfi_clean(x, oracle.RfiParams())
+    np.testing.assert_array_equal(r.fit, default.fit)
+    assert r.sigma == default.sigma
+
+
+def test_paper_beam_masks_exactly_its_bursts():
+    """1024-channel benchmark beam: three 5-channel bursts at +20 sigma.  One
+    round masks 10 channels and leaves sigma at 7.7 (the third burst hides
+    behind the first RMSE); the default masks exactly the 15 burst channels
+    and estimates the unit noise within 5 %."""
+    beam = synth.paper_beam()
+    s = oracle.delay_table(**beam.plan_kwargs())
+    x = synth.render(beam, s)
+    B = x.astype(np.float64).sum(axis=1) / x.shape[1]
+    burst = set()
+    for b in beam.bursts:
+        burst |= set(range(b.c0, b.c0 + b.nch))
+    one = oracle.fit_masked_bandpass(B, x.shape[1], oracle.RfiParams(mask_passes=1))
+    assert set(np.flatnonzero(one.masked)) < burst and one.sigma > 5.0
+    fit = oracle.fit_masked_bandpass(B, x.shape[1], oracle.RfiParams())
+    assert set(np.flatnonzero(fit.masked)) == burst
+    assert fit.sigma == pytest.approx(1.0, rel=0.05)
+
+
+@pytest.mark.slow
+def test_batch_beams_mask_exactly_their_bursts():
+    """The eight uneven u8 beams (noise std 16 in stored units): the default
+    masks exactly each beam's burst channels, and without the zero gap the
+    noise estimate is within 5 % of 16.  The gap (64 samples of 128 channels
+    set to 0) lowers those channels' means by 128*64/T, which the bandpass
+    residual, and so sigma, carries: the estimate may only rise with it."""
+    for beam in synth.batch_beams():
+        burst = set()
+        for b in beam.bursts:
+            burst |= set(range(b.c0, b.c0 + b.nch))
+        T = beam.nsamps
+        (gap,) = beam.gaps
+        beam.gaps = []
+        x = synth.render(beam, oracle.delay_table(**beam.plan_kwargs()))
+        S = x.sum(axis=1, dtype=np.float64)
+        # the gap zeroes a box of stored samples: subtract what it held
+        box = x[gap.c0:gap.c0 + gap.nch, gap.t0:gap.t0 + gap.length].sum(axis=1, dtype=np.float64)
+        del x
+        Sg = S.copy()
+        Sg[gap.c0:gap.c0 + gap.nch] -= box
+        fit = oracle.fit_masked_bandpass(Sg / T, T, oracle.RfiParams())
+        assert set(np.flatnonzero(fit.masked)) == burst, beam.name
+        clean = oracle.fit_masked_bandpass(S / T, T, oracle.RfiParams())
+        assert set(np.flatnonzero(clean.masked)) == burst, beam.name
+        assert clean.sigma == pytest.approx(synth.U8_STD, rel=0.05), beam.name
+        assert fit.sigma >= clean.sigma * 0.999, beam.name
+
+
 def test_degenerate_inputs_rejected():
     with pytest.raises(ValueError):
         oracle.rfi_clean(np.zeros((4, 100)), oracle.RfiParams(poly_order=3))
