@@ -339,3 +339,55 @@ def poisson_run(server: Server, chunks_per_beam: dict, tsamp_s: float, speedup: 
                launches=server.stats["launches"], chunks=server.stats["chunks"],
                dropped=server.stats["dropped"], stream_restarts=server.stats["stream_restarts"])
     return res
+
+
+def single_beam_run(plan: A.Plan, chunks, tsamp_s: float, speedup: float, seed: int = 0, nsigma: float = 6.0,
+                    capacity: int = 1 << 15, wall_limit: float = 300.0) -> dict:
+    """The plain path, for comparison with the server: one beam, each chunk
+    processed eagerly on one stream as soon as it has arrived and the previous
+    one is done (copy to the device, RFI pass, dedispersion with
+    normalisation, detection, candidates back to the host).  Arrivals are
+    Poisson with mean gap L * tsamp / speedup; latency runs from a chunk's
+    arrival to its candidates on the host.  chunks: host [C][L] tensors
+    (pinned) in stream order."""
+    rng = np.random.default_rng(seed)
+    t_arr, t = [], 0.0
+    for ch in chunks:
+        t += rng.exponential(ch.shape[1] * tsamp_s / speedup)
+        t_arr.append(t)
+    Lmax = max(ch.shape[1] for ch in chunks)
+    tdt = A.TORCH_DTYPES[plan.dtype]
+    xbuf = torch.empty(plan.nchans * Lmax, dtype=tdt, device=plan.device)
+    state = plan.alloc_rfi_state(Lmax)
+    out = plan.alloc_output(Lmax)
+    norm = plan.alloc_norm()
+    det = plan.alloc_detect(capacity)
+    h_count = torch.empty(1, dtype=torch.int64).pin_memory()
+    h_cands = torch.empty(det[0].numel(), dtype=torch.uint8).pin_memory()
+    beam = A.Beam(plan)
+    stream = torch.cuda.Stream(device=plan.device)
+    lat, dm_samples = [], 0
+    t0 = time.perf_counter()
+    for ta, ch in zip(t_arr, chunks):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0001)
+        L_ = ch.shape[1]
+        with torch.cuda.stream(stream):
+            x = xbuf[:plan.nchans * L_].view(plan.nchans, L_)
+            x.copy_(ch, non_blocking=True)
+            plan.rfi_threshold(x, state, stream=stream)
+            _, _, nout, s0 = plan.execute(x, rfi_state=state, out=out, norm=norm, beam=beam, stream=stream)
+            plan.detect(out, nout, norm, nsigma, sample0=s0, buffers=det, stream=stream)
+            h_count.copy_(det[1], non_blocking=True)
+            h_cands.copy_(det[0], non_blocking=True)
+        stream.synchronize()
+        lat.append(time.perf_counter() - (t0 + ta))
+        dm_samples += nout * plan.ndms
+        if time.perf_counter() - t0 > wall_limit:
+            raise TimeoutError("single-beam run exceeded its wall-clock limit")
+    wall = time.perf_counter() - t0
+    ms = np.array(lat) * 1e3
+    beam.close()
+    return {"p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+            "mean_ms": float(ms.mean()), "max_ms": float(ms.max()), "n": int(ms.size), "speedup": speedup,
+            "wall_s": wall, "dm_trial_samples_per_s": dm_samples / wall}

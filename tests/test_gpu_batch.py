@@ -7,7 +7,7 @@ import torch
 import oracle
 from paper_1307_5700_amd import synth
 
-from gpu_util import api, err_sigma, rfi_params, to_dev
+from gpu_util import api, err_noise, err_sigma, rfi_params, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +111,41 @@ def test_batch_rejects_mixed_tilings_and_types():
     p1b = A.Plan.from_beam(b1, tile_hint=1)
     with pytest.raises(A.L.MbError):
         A.execute_batch([dict(plan=p0, x=x0, rfi_state=p0.rfi_threshold(x0)), dict(plan=p1b, x=x1)])
+
+
+@pytest.mark.timeout(600)
+def test_batch_at_full_shape_matches_oracle_on_sampled_rows():
+    """The eight uneven uint8 beams at their full shapes (512-2048 channels,
+    320-1280 DMs, 16384-131072 samples, pulses, RFI and a zero gap), RFI
+    pass on, in one batched launch: every beam's flags equal the oracle's and
+    sampled DM rows equal its dedispersion within 1e-5."""
+    A = api()
+    beams = synth.batch_beams("u8")
+    plans = [A.Plan.from_beam(b, tile_hint=1) for b in beams]
+    jobs, hosts = [], []
+    for b, p in zip(beams, plans):
+        s = oracle.delay_table(**b.plan_kwargs())
+        assert np.array_equal(p.delays(), s)
+        xh = synth.render(b, s)
+        x = to_dev(xh)
+        jobs.append(dict(plan=p, x=x, rfi_state=p.rfi_threshold(x)))
+        hosts.append((xh, s))
+    res = A.execute_batch(jobs)
+    torch.cuda.synchronize()
+    for (b, p, j, (xh, s), (out, norm, nout, s0)) in zip(beams, plans, jobs, hosts, res):
+        assert s0 == 0 and nout == b.nsamps - int(s.max()), b.name
+        r = oracle.rfi_clean(xh, rfi_params(p.rfi_config))
+        g = p.rfi_arrays(j["rfi_state"], b.nsamps)
+        t = r.near_ties
+        assert t.get("chunk_count", 0) == 0 and t.get("spectrum_count", 0) == 0 and t.get("mask_count", 0) == 0
+        assert np.array_equal(g["masked"], r.masked), b.name
+        assert np.array_equal(g["chunk_flags_ext"], r.chunk_flags_ext), b.name
+        assert np.array_equal(g["spectrum_flags"], r.spectrum_flags), b.name
+        rows = sorted(set([0, b.ndms // 2, b.ndms - 1] + [q.dm_index for q in b.pulses]))
+        ref = oracle.dedisperse_rows(r.y, s, rows, nout)
+        got = out[rows, :nout].cpu().numpy()
+        assert err_sigma(got, ref) < 1e-5, b.name
+        assert err_noise(got, ref) < 1e-5, b.name
+        del r, ref, got, xh
+    del jobs, res
+    torch.cuda.empty_cache()

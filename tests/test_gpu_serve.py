@@ -159,10 +159,13 @@ def test_backlog_bound_drops_and_keeps_absolute_samples(drop):
     sample indices."""
     from paper_1307_5700_amd import serve
     A = api()
-    beams = _beams(1)
-    b, chunks = beams[0]
-    plan = A.Plan.from_beam(b)
+    b, _ = _beams(1)[0]
     starts = np.concatenate([[0], np.cumsum(LENS)]).tolist()
+    # a second pulse in the last two chunks, which both policies serve
+    b.pulses = b.pulses + [synth.Pulse(dm_index=30, t0=17000, width=3, amp=1.0)]
+    x = synth.render(b, oracle.delay_table(**b.plan_kwargs()))
+    chunks = [np.ascontiguousarray(x[:, a:a + L_]) for a, L_ in zip(starts, LENS)]
+    plan = A.Plan.from_beam(b)
     srv = serve.Server(plan, max_chunk=max(LENS), hbm_budget=8 << 30, nsigma=5.0, max_slots=2,
                        max_backlog=2, drop=drop)
     assert srv.add_beam(0)
@@ -187,7 +190,8 @@ def test_backlog_bound_drops_and_keeps_absolute_samples(drop):
         ref.update(_oracle_stream([chunks[k] for k in run], delays, rfi_params(plan.rfi_config), 5.0, dms,
                                   base=starts[run[0]]))
     _check_served(res, ref, 0)
-    assert sum(len(v[1]) for v in ref.values()) > 0
+    assert any(np.any((v[1]["dm_index"] == 30) & (v[1]["sample"] >= 17000) & (v[1]["sample"] < 17003))
+               for v in ref.values())
 
 
 def test_admission_waits_for_budget():
