@@ -456,6 +456,25 @@ mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nou
                             int64_t* d_count, mb_peak* d_peaks, void* d_work,
                             size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * detection as detect_candidates, with the same arguments, outputs and
+ * errors, but no d_work.  Its counts and offsets live in a fixed device array
+ * inside the library (2 MiB, one copy per GPU, kept until the process ends),
+ * so the plan may have at most MB_DETECT_NOALLOC_MAX_DMS DMs (else
+ * MB_EINVAL).  The call allocates nothing: the array's device address is
+ * looked up once per device when a plan is created there (or on the first
+ * call on that device).  The current device must be the plan's (else
+ * MB_EINVAL).  Every call on one GPU shares that array, so calls whose work
+ * overlaps on one GPU (on different streams, or from different threads
+ * without ordering) race and must not be made; calls ordered on one stream
+ * are safe, since each call writes every count and offset it reads. */
+#define MB_DETECT_NOALLOC_MAX_DMS 8192
+mb_status detect_candidates_noalloc(const mb_plan* plan, const float* d_out, int64_t nout,
+                                    int64_t ld_out, const mb_norm* d_norm, int64_t sample0,
+                                    const int64_t* d_sample0, double nsigma, mb_candidate* d_cands,
+                                    int64_t capacity, int64_t* d_count, mb_peak* d_peaks, void* stream);
+
 /* ---- errors ------------------------------------------------------------ */
 
 const char* mb_status_str(mb_status s);

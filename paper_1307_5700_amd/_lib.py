@@ -62,6 +62,7 @@ class ExecInfo(ctypes.Structure):
     _fields_ = [("nout", c_i64), ("sample0", c_i64)]
 
 
+DETECT_NOALLOC_MAX_DMS = 8192   # MB_DETECT_NOALLOC_MAX_DMS
 NORM_BYTES = 32        # mb_norm: 3 doubles + 2 int32
 CANDIDATE_BYTES = 24   # mb_candidate
 PEAK_BYTES = 16        # mb_peak
@@ -104,6 +105,8 @@ _SIGS = {
     "detect_workspace_size": ([c_vp, ctypes.POINTER(c_sz)], c_i32),
     "detect_candidates": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_dbl, c_vp, c_i64, c_vp, c_vp,
                            c_vp, c_sz, c_vp], c_i32),
+    "detect_candidates_noalloc": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_dbl, c_vp, c_i64, c_vp,
+                                   c_vp, c_vp], c_i32),
     "mb_status_str": ([c_i32], ctypes.c_char_p),
     "mb_last_error": ([], ctypes.c_char_p),
 }

@@ -227,6 +227,21 @@ class Plan:
                 "detect_candidates")
         return cands, count, peaks, work
 
+    def detect_noalloc(self, out: torch.Tensor, nout: int, norm: torch.Tensor, nsigma: float,
+                       cands: torch.Tensor, count: torch.Tensor, peaks: torch.Tensor | None = None,
+                       sample0: int = 0, stream=None, beam: "Beam | None" = None):
+        """detect_candidates_noalloc: detection into caller buffers with no
+        workspace (the library's fixed scratch array, at most
+        DETECT_NOALLOC_MAX_DMS DMs); returns (cands, count, peaks)."""
+        cap = cands.numel() // L.CANDIDATE_BYTES
+        d_s0 = ctypes.c_void_p(beam.sample0_ptr()) if beam is not None else None
+        L.check(L.lib().detect_candidates_noalloc(self._h, _ptr(out), int(nout), out.stride(0), _ptr(norm),
+                                                  int(sample0), d_s0, float(nsigma), _ptr(cands), cap,
+                                                  _ptr(count), _ptr(peaks) if peaks is not None else None,
+                                                  _stream_ptr(stream)),
+                "detect_candidates_noalloc")
+        return cands, count, peaks
+
     @staticmethod
     def candidates_to_host(cands: torch.Tensor, count: torch.Tensor):
         n = int(count.item())

@@ -16,9 +16,19 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace mbtp {
+
+// The allocation-free detection's counts and offsets per (row, segment): a
+// fixed array, one copy on each GPU the library runs on, held until the
+// process ends.  Host code never passes this name to a kernel (on the host
+// it is only a handle of the symbol); it uses the device address that
+// detect_scratch_setup looked up for the current device.
+static __device__ __align__(256) int64_t scratch[2 * kDetectSegs * kDetectNoAllocMaxDms];
+
 namespace {
 
 constexpr double kDegenerateRtol = 1e-9;
@@ -329,6 +339,43 @@ hipError_t launch_detect(const float* out, int64_t ld_out, int64_t nout, int32_t
   hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)ndms), dim3(1024), 0, s, out, ld_out, nout,
                      norm, nsigma, sample0, d_sample0, dm_start, dm_step, counts, offsets, cands, capacity);
   return hipGetLastError();
+}
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices];   // device address of `scratch` per device
+}  // namespace
+
+hipError_t detect_scratch_setup(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *ptr = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_detect_noalloc(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
+                                 const NormDev* norm, int64_t sample0, const int64_t* d_sample0, double nsigma,
+                                 double dm_start, double dm_step, CandDev* cands, int64_t capacity,
+                                 int64_t* d_count, PeakDev* peaks, hipStream_t s) {
+  if (ndms < 1 || ndms > kDetectNoAllocMaxDms) return hipErrorInvalidValue;
+  void* work = nullptr;
+  hipError_t e = detect_scratch_setup(&work);
+  if (e != hipSuccess) return e;
+  // every (row, segment) count is written by the count pass and every offset
+  // by the scan before anything reads them, so nothing needs clearing
+  return launch_detect(out, ld_out, nout, ndms, norm, sample0, d_sample0, nsigma, dm_start, dm_step, cands,
+                       capacity, d_count, peaks, work, s);
 }
 
 }  // namespace mbtp

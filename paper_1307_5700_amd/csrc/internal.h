@@ -246,4 +246,20 @@ inline size_t detect_work_bytes(int32_t ndms) {
   return align256(sizeof(int64_t) * 2 * kDetectSegs * size_t(ndms));
 }
 
+// Most DM rows the allocation-free detection can take: its counts and
+// offsets live in a fixed device array of detect_work_bytes(this) = 2 MiB.
+constexpr int32_t kDetectNoAllocMaxDms = 8192;
+
+// Looks up, once per device, the device address of the allocation-free
+// detection's scratch array on the current device (no allocation).
+hipError_t detect_scratch_setup(void** ptr);
+
+// launch_detect with the counts and offsets in that scratch array (found
+// with detect_scratch_setup on the current device); ndms must not exceed
+// kDetectNoAllocMaxDms.
+hipError_t launch_detect_noalloc(const float* out, int64_t ld_out, int64_t nout, int32_t ndms,
+                                 const NormDev* norm, int64_t sample0, const int64_t* d_sample0, double nsigma,
+                                 double dm_start, double dm_step, CandDev* cands, int64_t capacity,
+                                 int64_t* d_count, PeakDev* peaks, hipStream_t s);
+
 }  // namespace mbtp

@@ -203,6 +203,20 @@ mb_status validate_rfi(const mb_rfi_params& r, int C) {
   return MB_OK;
 }
 
+// Arguments shared by both detection entry points.
+mb_status validate_detect(const mb_plan* plan, const float* d_out, int64_t nout, int64_t ld_out,
+                          const mb_norm* d_norm, int64_t sample0, double nsigma, const mb_candidate* d_cands,
+                          int64_t capacity, const int64_t* d_count) {
+  if (!plan) return fail(MB_EINVAL, "plan is NULL");
+  if (nout < 0 || sample0 < 0) return fail(MB_EINVAL, "nout and sample0 must be >= 0");
+  if (nout > 0 && (!d_out || !check_aligned(d_out, 16) || ld_out < nout || ld_out % 4 != 0))
+    return fail(MB_EINVAL, "output plane must be 16-byte aligned with ld_out >= nout, ld_out %% 4 == 0");
+  if (!d_norm || !d_count) return fail(MB_EINVAL, "norm and count must not be NULL");
+  if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(MB_EINVAL, "capacity > 0 needs a candidate buffer");
+  if (!isfinite(nsigma)) return fail(MB_EINVAL, "nsigma must be finite");
+  return MB_OK;
+}
+
 mb_status validate_input(const mb_plan* plan, const void* d_in, int64_t nsamps, int64_t ld) {
   if (!plan) return fail(MB_EINVAL, "plan is NULL");
   if (!d_in) return fail(MB_EINVAL, "input pointer is NULL");
@@ -287,6 +301,10 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
   if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->tiling.copies(),
                                         p->relb_ld, p->d_relb, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  // the allocation-free detection's scratch address on this device, looked
+  // up here so that later calls (possibly under graph capture) only read it
+  void* scratch_dev = nullptr;
+  if (e == hipSuccess) e = detect_scratch_setup(&scratch_dev);
   if (e != hipSuccess) {
     (void)hipFree(p->d_delays);
     (void)hipFree(p->d_relb);
@@ -873,13 +891,8 @@ mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nou
                             const mb_norm* d_norm, int64_t sample0, const int64_t* d_sample0,
                             double nsigma, mb_candidate* d_cands, int64_t capacity, int64_t* d_count,
                             mb_peak* d_peaks, void* d_work, size_t work_bytes, void* stream) {
-  if (!plan) return fail(MB_EINVAL, "plan is NULL");
-  if (nout < 0 || sample0 < 0) return fail(MB_EINVAL, "nout and sample0 must be >= 0");
-  if (nout > 0 && (!d_out || !check_aligned(d_out, 16) || ld_out < nout || ld_out % 4 != 0))
-    return fail(MB_EINVAL, "output plane must be 16-byte aligned with ld_out >= nout, ld_out %% 4 == 0");
-  if (!d_norm || !d_count) return fail(MB_EINVAL, "norm and count must not be NULL");
-  if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(MB_EINVAL, "capacity > 0 needs a candidate buffer");
-  if (!isfinite(nsigma)) return fail(MB_EINVAL, "nsigma must be finite");
+  mb_status st = validate_detect(plan, d_out, nout, ld_out, d_norm, sample0, nsigma, d_cands, capacity, d_count);
+  if (st) return st;
   const size_t need = detect_work_bytes(plan->desc.ndms);
   if (!d_work || work_bytes < need || !check_aligned(d_work, 256))
     return fail(MB_EINVAL, "workspace must be 256-byte aligned with at least %zu bytes", need);
@@ -887,6 +900,26 @@ mb_status detect_candidates(const mb_plan* plan, const float* d_out, int64_t nou
                         sample0, d_sample0, nsigma, plan->desc.dm_start, plan->desc.dm_step,
                         reinterpret_cast<CandDev*>(d_cands), capacity, d_count,
                         reinterpret_cast<PeakDev*>(d_peaks), d_work, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mb_status detect_candidates_noalloc(const mb_plan* plan, const float* d_out, int64_t nout, int64_t ld_out,
+                                    const mb_norm* d_norm, int64_t sample0, const int64_t* d_sample0,
+                                    double nsigma, mb_candidate* d_cands, int64_t capacity, int64_t* d_count,
+                                    mb_peak* d_peaks, void* stream) {
+  mb_status st = validate_detect(plan, d_out, nout, ld_out, d_norm, sample0, nsigma, d_cands, capacity, d_count);
+  if (st) return st;
+  if (plan->desc.ndms > MB_DETECT_NOALLOC_MAX_DMS)
+    return fail(MB_EINVAL, "detect_candidates_noalloc takes at most %d DMs (plan has %d)",
+                MB_DETECT_NOALLOC_MAX_DMS, plan->desc.ndms);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device)
+    return fail(MB_EINVAL, "current device %d is not the plan's device %d", dev, plan->device);
+  HIP_TRY(launch_detect_noalloc(d_out, ld_out, nout, plan->desc.ndms, reinterpret_cast<const NormDev*>(d_norm),
+                                sample0, d_sample0, nsigma, plan->desc.dm_start, plan->desc.dm_step,
+                                reinterpret_cast<CandDev*>(d_cands), capacity, d_count,
+                                reinterpret_cast<PeakDev*>(d_peaks), static_cast<hipStream_t>(stream)));
   return ok();
 }
 
