@@ -158,6 +158,34 @@ def test_paper_beam_full_plane():
             assert p.t0 - 2 <= g["peaks"]["sample"][p.dm_index] < p.t0 + p.width + 2
 
 
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+def test_tiling_does_not_change_a_bit_without_rfi(dtype):
+    """Without the RFI pass, every compiled tiling gives the same bits too
+    (the uncleaned staging paths, FP32 and uint8)."""
+    A = api()
+    beam = synth.paper_beam(dtype=dtype, nsamps=16384)
+    beam.ndms = 200
+    beam.rfi = False
+    beam.pulses = [p for p in beam.pulses if p.dm_index < 200]
+    x, _ = beam_input(beam)
+    xd = to_dev(x)
+    ref = None
+    used = set()
+    for hint in range(1, A.num_tilings() + 1):
+        try:
+            plan = A.Plan.from_beam(beam, tile_hint=hint)
+        except A.L.MbError:
+            continue
+        used.add(plan.tiling["index"])
+        out, norm, nout, _ = plan.execute(xd)
+        D = out[:, :nout].cpu().numpy()
+        if ref is None:
+            ref = D
+        else:
+            assert np.array_equal(D, ref), hint
+    assert len(used) >= 4
+
+
 def test_tiling_does_not_change_a_bit():
     A = api()
     beam = synth.paper_beam(nsamps=16384)
