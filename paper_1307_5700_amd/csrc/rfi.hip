@@ -368,6 +368,231 @@ __global__ __launch_bounds__(1024) void rfi_fit_kernel(int64_t C, int64_t T, Rfi
   }
 }
 
+// The same fit-and-mask rounds for up to kFitRegMaxC channels with the
+// interpolated bandpass in registers: thread k owns channels k, k + 1024,
+// ... (KC of them), the mask is mirrored in LDS for the neighbour search,
+// and every thread solves the tiny normal equations itself, so a round is
+// two block sums and two block-wide ORs.  The sums run over the same
+// per-thread partials and the same reduction tree as rfi_fit_kernel, so
+// both give the same fit.
+constexpr int64_t kFitRegMaxC = 2048;
+
+template <int D>
+__device__ inline void cholesky_packed(const double* G, double* L) {
+  constexpr int N = D + 1;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double v = G[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[tri(i, k)] * L[tri(j, k)];
+      if (i == j) L[tri(i, i)] = sqrt(v > 0.0 ? v : 0.0);
+      else L[tri(i, j)] = v / L[tri(j, j)];
+    }
+}
+
+template <int D>
+__device__ inline void chol_solve(const double* L, const double* h, double* x) {
+  constexpr int N = D + 1;
+  double y[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double t = h[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= L[tri(i, k)] * y[k];
+    y[i] = t / L[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double t = y[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) t -= L[tri(k, i)] * x[k];
+    x[i] = t / L[tri(i, i)];
+  }
+}
+
+template <int D, int KC>
+__global__ __launch_bounds__(1024) void rfi_fit_reg_kernel(int64_t C, int64_t T, RfiParamsDev prm,
+                                                           const double* __restrict__ bsum,
+                                                           double* __restrict__ binterp,
+                                                           double* __restrict__ fit,
+                                                           float* __restrict__ fit32,
+                                                           uint8_t* __restrict__ masked,
+                                                           RfiHeader* __restrict__ hdr) {
+  constexpr int N = D + 1, NG = N * (N + 1) / 2;
+  __shared__ double sh[17 * NG + 17];
+  __shared__ uint8_t msk[kFitRegMaxC];
+  const int tid = threadIdx.x;
+  const double invT = 1.0 / (double)T;
+  double bi[KC];
+  uint32_t mine = 0;                         // bit k: channel tid + 1024k is masked
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int64_t c = tid + 1024 * k;
+    bi[k] = c < C ? bsum[c] * invT : 0.0;
+    if (c < C) msk[c] = 0;
+  }
+  // Gram matrix of the Legendre basis over the channel positions, factored
+  // by every thread
+  double L[NG];
+  {
+    double Gl[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) Gl[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = tid + 1024 * k;
+      if (c < C) {
+        double P[N];
+        legendre<D>(u_of(c, C), P);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) Gl[tri(i, j)] += P[i] * P[j];
+      }
+    }
+    double G[NG];
+    block_sums_1024<NG>(Gl, sh, G);
+    cholesky_packed<D>(G, L);
+  }
+  // least-squares coefficients of bi and the RMSE of bi - fit
+  double coef[N];
+  auto fit_round = [&]() -> double {
+    double hl[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) hl[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = tid + 1024 * k;
+      if (c < C) {
+        double P[N];
+        legendre<D>(u_of(c, C), P);
+#pragma unroll
+        for (int i = 0; i < N; ++i) hl[i] += P[i] * bi[k];
+      }
+    }
+    double h[N];
+    block_sums_1024<N>(hl, sh, h);
+    chol_solve<D>(L, h, coef);
+    double ssq[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = tid + 1024 * k;
+      if (c < C) {
+        double P[N];
+        legendre<D>(u_of(c, C), P);
+        double f = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) f += coef[i] * P[i];
+        const double r = bi[k] - f;
+        ssq[0] += r * r;
+      }
+    }
+    double tot[1];
+    block_sums_1024<1>(ssq, sh, tot);
+    return sqrt(tot[0] / (double)C);
+  };
+  auto fit_at = [&](int64_t c) {
+    double P[N];
+    legendre<D>(u_of(c, C), P);
+    double f = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) f += coef[i] * P[i];
+    return f;
+  };
+  double rmse0 = 0.0, rmse = 0.0;
+  int any_left = 1;
+  bool settled = false;
+  const int passes = prm.mask_passes < 1 ? 1 : prm.mask_passes;
+  for (int pass = 0; pass < passes; ++pass) {
+    const double rmse_i = fit_round();
+    if (pass == 0) rmse0 = rmse_i;
+    rmse = rmse_i;
+    const double thr = prm.k_mask * rmse_i;
+    int bits = 0;                            // bit 0: an unmasked channel is left; bit 1: the mask grew
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = tid + 1024 * k;
+      if (c < C) {
+        if (!((mine >> k) & 1u) && fabs(bsum[c] * invT - fit_at(c)) > thr) {
+          mine |= 1u << k;
+          msk[c] = 1;
+          bits |= 2;
+        }
+        bits |= ((mine >> k) & 1u) ? 0 : 1;
+      }
+    }
+    // the block-wide ORs also publish msk[]
+    const int all = __syncthreads_or(bits & 1) | (__syncthreads_or(bits & 2) ? 2 : 0);
+    any_left = all & 1;
+    if (!any_left) break;
+    if (!(all & 2)) { settled = true; break; }
+    // masked channels take the mean of their nearest unmasked neighbours
+    // (one side at a band edge); the others keep their own mean
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = tid + 1024 * k;
+      if (c < C && ((mine >> k) & 1u)) {
+        int64_t l = c - 1, r = c + 1;
+        while (l >= 0 && msk[l]) --l;
+        while (r < C && msk[r]) ++r;
+        double v;
+        if (l >= 0 && r < C) v = (bsum[l] * invT + bsum[r] * invT) * 0.5;
+        else if (l >= 0) v = bsum[l] * invT;
+        else v = bsum[r] * invT;
+        bi[k] = v;
+      }
+    }
+  }
+  if (tid == 0) {
+    hdr->nsamps = T;
+    hdr->nchunks = (T + prm.W - 1) / prm.W;
+  }
+  if (!any_left) {
+    for (int64_t c = tid; c < C; c += 1024) {
+      fit32[c] = 0.0f;
+      masked[c] = 1;
+      binterp[c] = bsum[c] * invT;
+    }
+    if (tid == 0) {
+      hdr->error = 1; hdr->sigma = 0.0; hdr->rmse0 = rmse0; hdr->rmse = 0.0;
+      hdr->sum_fit = 0.0; hdr->thr_spec = 0.0; hdr->k_chan = prm.k_chan;
+      hdr->n_masked = (unsigned long long)C; hdr->n_chunk = hdr->n_chunk_ext = hdr->n_spec = 0;
+    }
+    return;
+  }
+  if (!settled) rmse = fit_round();
+  double sums[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int64_t c = tid + 1024 * k;
+    if (c < C) {
+      const double f = fit_at(c);
+      fit[c] = f;
+      fit32[c] = (float)f;
+      binterp[c] = bi[k];
+      masked[c] = (uint8_t)((mine >> k) & 1u);
+      sums[0] += f;
+      sums[1] += ((mine >> k) & 1u) ? 1.0 : 0.0;
+    }
+  }
+  double tot[2];
+  block_sums_1024<2>(sums, sh, tot);
+  if (tid == 0) {
+    const double sigma = rmse * sqrt((double)T * (double)C / (double)(C - prm.p - 1));
+    hdr->sigma = sigma;
+    hdr->rmse0 = rmse0;
+    hdr->rmse = rmse;
+    hdr->sum_fit = tot[0];
+    hdr->thr_spec = prm.k_spec * sigma / sqrt((double)C);
+    hdr->k_chan = prm.k_chan;
+    hdr->n_masked = (unsigned long long)tot[1];
+    hdr->n_chunk = hdr->n_chunk_ext = hdr->n_spec = 0;
+    hdr->error = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Chunk flags: one workgroup per chunk j, threads over channels.  F[c][j] is
 // |M[c][j]/L_j - f_c| > k_chan*sigma/sqrt(L_j); the extended flag also takes
@@ -452,8 +677,22 @@ __global__ __launch_bounds__(256) void rfi_spectrum_flags_kernel(
     const int64_t j = t / W;
     double corr = 0.0;
     const int n = lcount[j];
-    for (int k = 0; k < n; ++k) {
-      const int64_t c = list[j * C + k];
+    const int32_t* lj = list + j * C;
+    // the flagged channels of the chunk in ascending order, eight loads in
+    // flight at a time; the additions keep that order
+    int k = 0;
+    for (; k + 8 <= n; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t c = lj[k + u];
+        v[u] = Vec4Load<TIN>::one(x + c * ld + t) - fit[c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) corr += v[u];
+    }
+    for (; k < n; ++k) {
+      const int64_t c = lj[k];
       corr += Vec4Load<TIN>::one(x + c * ld + t) - fit[c];
     }
     const double s = ((S - hdr->sum_fit) - corr) / (double)C;
@@ -486,6 +725,27 @@ __global__ __launch_bounds__(256) void rfi_chunk_bits_kernel(const uint8_t* __re
   cbits[i] = word;
 }
 
+// The register-resident fit where its registers hold without spilling
+// (degree <= 4, up to 2048 channels), else the fit through global memory.
+template <int D>
+void launch_fit(const RfiGeom& g, const RfiParamsDev& prm, const double* bsum, double* binterp, double* fit,
+                float* fit32, uint8_t* masked, RfiHeader* hdr, hipStream_t s) {
+  if constexpr (D <= 4) {
+    if (g.C <= 1024) {
+      hipLaunchKernelGGL((rfi_fit_reg_kernel<D, 1>), dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, binterp, fit,
+                         fit32, masked, hdr);
+      return;
+    }
+    if (g.C <= 2048) {
+      hipLaunchKernelGGL((rfi_fit_reg_kernel<D, 2>), dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, binterp, fit,
+                         fit32, masked, hdr);
+      return;
+    }
+  }
+  hipLaunchKernelGGL(rfi_fit_kernel<D>, dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, binterp, fit, fit32,
+                     masked, hdr);
+}
+
 template <typename TIN>
 hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiParamsDev& prm,
                         char* st, hipStream_t s) {
@@ -510,8 +770,7 @@ hipError_t launch_rfi_t(const TIN* x, int64_t ld, const RfiGeom& g, const RfiPar
                      span_sum, g.C, g.nspans, g.W / kSpan, g.J, chunk, bsum);
   switch (prm.p) {
 #define MBTP_FIT(D_) \
-    case D_: hipLaunchKernelGGL(rfi_fit_kernel<D_>, dim3(1), dim3(1024), 0, s, g.C, g.T, prm, bsum, \
-                                binterp, fit, fit32, masked, hdr); break;
+    case D_: launch_fit<D_>(g, prm, bsum, binterp, fit, fit32, masked, hdr, s); break;
     MBTP_FIT(0) MBTP_FIT(1) MBTP_FIT(2) MBTP_FIT(3) MBTP_FIT(4) MBTP_FIT(5) MBTP_FIT(6)
     MBTP_FIT(7) MBTP_FIT(8)
 #undef MBTP_FIT
