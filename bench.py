@@ -961,6 +961,22 @@ def bench_cluster(args):
     torch.cuda.synchronize()
     c_ms = e0.elapsed_time(e1) / args.steps
     cls = info.cpu().numpy().view(A.CLUSTER_INFO_DTYPE)["cls"]
+    # the paper's FDBSCAN (expansion from representative points) on the same
+    # list, timed the same way; its labels against the exact DBSCAN's
+    flab, fnc, fnq = A.fdbscan_candidates(buf, n, ndms, te, de, se, mp)
+    for _ in range(args.warmup):
+        A.fdbscan_candidates(buf, n, ndms, te, de, se, mp, labels=flab)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        A.fdbscan_candidates(buf, n, ndms, te, de, se, mp, labels=flab)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    f_ms = e0.elapsed_time(e1) / args.steps
+    fl, el = flab.cpu().numpy(), labels.cpu().numpy()
+    fdb = {"kernel_ms": f_ms, "clusters": int(fnc.item()), "region_queries": int(fnq.item()),
+           "lost_vs_dbscan": int(((el >= 0) & (fl < 0)).sum()),
+           "relabelled_vs_dbscan": int(((el >= 0) & (fl >= 0) & (fl != el)).sum())}
     nbytes = n * (24 + 4)                  # read every record once, write its label
     t0 = time.perf_counter()
     reps = 0
@@ -978,7 +994,8 @@ def bench_cluster(args):
              "kernel_ms": k_ms,
              "classify": {"kernel_ms": c_ms, "clusters": nclusters, "candidates": int((cls == 0).sum()),
                           "rfi_low_dm": int((cls == 1).sum()), "rfi_rmse": int((cls == 2).sum()),
-                          "k": 3, "rmse_max": 0.2, "dm_min": 1.0}}
+                          "k": 3, "rmse_max": 0.2, "dm_min": 1.0},
+             "fdbscan": fdb}
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = {"value": n / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
                                  "sample": f"the full list of {n} points, {reps} passes in {cpu_s * reps:.1f} s "

@@ -315,6 +315,32 @@ mb_status cluster_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndm
                              float snr_eps, int32_t min_pts, int32_t* d_labels, int32_t* d_nclusters,
                              void* d_work, size_t work_bytes, void* stream);
 
+/* FDBSCAN clustering of detections as the paper runs it (Sec. 2.3), with
+ * the inputs, neighbourhoods and core points of cluster_candidates.  Points
+ * are visited in index order; an unclassified point that is not a core point
+ * is region-queried and left unclassified; an unclassified core point starts
+ * a new cluster, which every unlabelled member of its neighbourhood joins;
+ * the cluster then grows only from representatives: for each dimension
+ * (sample, DM index, SNR, the SNR offset in FP32) and each direction, the
+ * member of the expanding point's neighbourhood lying farthest from it (the
+ * lowest index among equally far ones; none where no member lies off the
+ * point in that direction).  Every representative is region-queried at most
+ * once; a core one adds its unlabelled neighbours to the cluster and its own
+ * representatives to the seeds.  Points left unclassified are noise.  Unlike
+ * cluster_candidates this can lose a border point or split a cluster that
+ * is reachable only through a core point that is never a representative.
+ * d_labels [n] receives -1 for noise, else the cluster number in order of
+ * creation; d_nclusters (device int32) the cluster count; d_nqueries
+ * (device int64, nullable, 8-byte aligned) the number of region queries.
+ * d_work: fdbscan_workspace_size bytes, 256-byte aligned, caller-owned.  The
+ * visiting order runs on one workgroup.  Asynchronous on stream; the result
+ * is a function of the input alone.  Errors: as cluster_candidates, and
+ * MB_EINVAL for t_eps >= 2^31. */
+mb_status fdbscan_workspace_size(int64_t n, int32_t ndms, size_t* bytes);
+mb_status fdbscan_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps,
+                             float snr_eps, int32_t min_pts, int32_t* d_labels, int32_t* d_nclusters,
+                             int64_t* d_nqueries, void* d_work, size_t work_bytes, void* stream);
+
 /* Per-cluster result of the DM-SNR classification. */
 typedef struct {
   int32_t peak_dm_index;  /* row with the most detections (ties: larger SNR, then lower index) */

@@ -87,6 +87,9 @@ _SIGS = {
     "cluster_workspace_size": ([c_i64, c_i32, ctypes.POINTER(ctypes.c_size_t)], c_i32),
     "cluster_candidates": ([c_vp, c_i64, c_i32, c_i64, c_i32, ctypes.c_float, c_i32, c_vp, c_vp, c_vp,
                             ctypes.c_size_t, c_vp], c_i32),
+    "fdbscan_workspace_size": ([c_i64, c_i32, ctypes.POINTER(ctypes.c_size_t)], c_i32),
+    "fdbscan_candidates": ([c_vp, c_i64, c_i32, c_i64, c_i32, ctypes.c_float, c_i32, c_vp, c_vp, c_vp, c_vp,
+                            ctypes.c_size_t, c_vp], c_i32),
     "classify_clusters": ([c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                            ctypes.c_double, ctypes.c_double, c_i32, ctypes.c_double, ctypes.c_double, c_vp, c_vp],
                           c_i32),

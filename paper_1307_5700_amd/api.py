@@ -286,6 +286,29 @@ def cluster_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_ep
     return labels[:n], nclusters
 
 
+def fdbscan_candidates(cands: torch.Tensor, n: int, ndms: int, t_eps: int, dm_eps: int, snr_eps: float,
+                       min_pts: int, labels: torch.Tensor | None = None, stream=None):
+    """FDBSCAN clustering (Sec. 2.3, expansion from representative points)
+    of the first n candidate records of a device buffer in (dm_index,
+    sample) order: returns (labels int32 [n], -1 for noise; nclusters int32
+    [1]; nqueries int64 [1])."""
+    dev = cands.device
+    if cands.numel() < n * L.CANDIDATE_BYTES:
+        raise ValueError("cands holds fewer than n records")
+    labels = torch.empty(max(int(n), 1), dtype=torch.int32, device=dev) if labels is None else labels
+    if labels.dtype != torch.int32 or labels.numel() < n:
+        raise ValueError("labels must be int32 with room for n labels")
+    nclusters = torch.empty(1, dtype=torch.int32, device=dev)
+    nqueries = torch.empty(1, dtype=torch.int64, device=dev)
+    nb = ctypes.c_size_t()
+    L.check(L.lib().fdbscan_workspace_size(int(n), int(ndms), ctypes.byref(nb)), "fdbscan_workspace_size")
+    work = _alloc(nb.value, dev)
+    L.check(L.lib().fdbscan_candidates(_ptr(cands), int(n), int(ndms), int(t_eps), int(dm_eps), float(snr_eps),
+                                       int(min_pts), _ptr(labels), _ptr(nclusters), _ptr(nqueries), _ptr(work),
+                                       work.numel(), _stream_ptr(stream)), "fdbscan_candidates")
+    return labels[:n], nclusters, nqueries
+
+
 CLUSTER_INFO_DTYPE = np.dtype([("peak_dm_index", "<i4"), ("npoints", "<i4"), ("ndm_rows", "<i4"), ("cls", "<i4"),
                                ("t_first", "<i8"), ("t_last", "<i8"), ("peak_snr", "<f4"), ("reserved", "<i4"),
                                ("rmse", "<f8")])

@@ -248,6 +248,164 @@ __global__ __launch_bounds__(256) void cluster_label_kernel(int32_t n, const int
   labels[i] = r < 0 ? -1 : rank[r];
 }
 
+// ---- FDBSCAN (Sec. 2.3) ------------------------------------------------------
+// The paper's FDBSCAN: points are visited in index order; an unclassified
+// core point starts a cluster, every unlabelled member of its neighbourhood
+// joins it, and the expansion continues only from the representatives of a
+// neighbourhood: with the expanding point at the origin, the member lying
+// farthest in each direction of each dimension (sample, DM index, SNR; SNR
+// offsets in FP32), the lowest index among equally far ones.  A point is
+// region-queried at most once.
+//
+// A point's representatives depend on the data alone, so they are formed
+// for every core point in parallel beforehand (fdb_reps_kernel).  What
+// follows the visiting order runs on one workgroup (fdb_expand_kernel): it
+// finds the next unclassified core point in index order and expands its
+// cluster level by level.  Within a cluster every join writes the same
+// number, and the points expanded are the closure of the start point under
+// "representative of an expanded core point not queried before", which does
+// not depend on the order the queue is served in; so labels, cluster count
+// and query count equal those of the sequential algorithm.
+constexpr int32_t kFdbUnclassified = -2;
+
+// Key of a representative: its positive offset in the high word, the
+// complement of its index in the low word, so an atomic maximum keeps the
+// farthest member and, among equally far ones, the lowest index.  0: none.
+__device__ inline uint64_t fdb_key(uint32_t off_bits, int32_t j) {
+  return ((uint64_t)off_bits << 32) | (uint64_t)(0xffffffffu - (uint32_t)j);
+}
+
+__global__ __launch_bounds__(256) void fdb_init_kernel(int32_t n, int32_t* __restrict__ cnt,
+                                                       uint64_t* __restrict__ keys, int32_t* __restrict__ queried,
+                                                       int32_t* __restrict__ labels) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  cnt[i] = 0;
+  queried[i] = 0;
+  labels[i] = kFdbUnclassified;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) keys[6 * (int64_t)i + k] = 0;
+}
+
+// Representatives of every core point: per (point, DM row) the row's
+// farthest members in the six directions, combined over the rows with 64-bit
+// atomic maxima (order-independent).  keys[6i + k]: k = 0/1 sample +/-,
+// 2/3 DM index +/-, 4/5 SNR +/-.
+__global__ __launch_bounds__(256) void fdb_reps_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
+                                                       uint64_t* __restrict__ keys) {
+  for_point_rows(A, [&](int32_t i, const CandDev& p, int32_t dd) {
+    if (cnt[i] < A.min_pts) return;
+    uint64_t k[6] = {0, 0, 0, 0, 0, 0};
+    for_row(A, p, dd, [&](int32_t j) {
+      const CandDev& q = A.c[j];
+      const int64_t ds = q.sample - p.sample;
+      const int32_t dm = q.dm_index - p.dm_index;
+      const float dq = q.snr - p.snr;                 // FP32, as stored
+      if (ds > 0) k[0] = max(k[0], fdb_key((uint32_t)ds, j));
+      if (ds < 0) k[1] = max(k[1], fdb_key((uint32_t)(-ds), j));
+      if (dm > 0) k[2] = max(k[2], fdb_key((uint32_t)dm, j));
+      if (dm < 0) k[3] = max(k[3], fdb_key((uint32_t)(-dm), j));
+      if (dq > 0.0f) k[4] = max(k[4], fdb_key(__float_as_uint(dq), j));
+      if (-dq > 0.0f) k[5] = max(k[5], fdb_key(__float_as_uint(-dq), j));
+    });
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+      if (k[m]) atomicMax(reinterpret_cast<unsigned long long*>(keys + 6 * (int64_t)i + m), (unsigned long long)k[m]);
+  });
+}
+
+// The visiting order, on one 1024-thread workgroup.  Unclassified non-core
+// points that the sequential scan passes are region-queried there (counted,
+// marked) and stay unclassified until a cluster takes them or the end makes
+// them noise.
+__global__ __launch_bounds__(1024) void fdb_expand_kernel(ClusterArgs A, const int32_t* __restrict__ cnt,
+                                                          const uint64_t* __restrict__ keys,
+                                                          int32_t* __restrict__ queried, int32_t* __restrict__ fa,
+                                                          int32_t* __restrict__ fb, int32_t* __restrict__ labels,
+                                                          int32_t* __restrict__ nclusters,
+                                                          int64_t* __restrict__ nqueries) {
+  __shared__ int32_t s_first, s_next, s_seeds;
+  __shared__ int32_t s_cnt[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int32_t n = A.n;
+  const int64_t R = 2 * (int64_t)A.dm_eps + 1;
+  int32_t cursor = 0, ncl = 0;
+  int64_t nq = 0;                                  // kept by thread 0
+  for (;;) {
+    // the next unclassified core point at or after the cursor
+    int32_t first = n;
+    for (int32_t base = cursor; base < n && first == n; base += 1024) {
+      const int32_t i = base + tid;
+      const bool unl = i < n && labels[i] == kFdbUnclassified;
+      const bool core = unl && cnt[i] >= A.min_pts;
+      if (tid == 0) s_first = n;
+      __syncthreads();
+      if (core) atomicMin(&s_first, i);
+      __syncthreads();
+      const int32_t f = s_first;
+      const bool visited = unl && !core && i < f;
+      if (visited) queried[i] = 1;
+      const int c = __popcll(__ballot(visited));
+      if (lane == 0) s_cnt[w] = c;
+      __syncthreads();
+      if (tid == 0)
+        for (int k = 0; k < 16; ++k) nq += s_cnt[k];
+      first = f;
+      __syncthreads();
+    }
+    if (first == n) break;
+    cursor = first + 1;
+    const int32_t cid = ncl++;
+    if (tid == 0) {
+      queried[first] = 1;
+      nq += 1;
+      fa[0] = first;
+    }
+    int32_t* cur = fa;
+    int32_t* nxt = fb;
+    int32_t nfront = 1;
+    __syncthreads();
+    while (nfront > 0) {
+      if (tid == 0) { s_next = 0; s_seeds = 0; }
+      // every member of the frontier points' neighbourhoods that carries no
+      // label joins the cluster (all writers write cid)
+      const int64_t items = (int64_t)nfront * R;
+      for (int64_t t = tid; t < items; t += 1024) {
+        const int32_t f = cur[t / R];
+        const CandDev p = A.c[f];
+        const int64_t dd = (int64_t)p.dm_index - A.dm_eps + t % R;
+        if (dd < 0 || dd >= A.ndms) continue;
+        for_row(A, p, (int32_t)dd, [&](int32_t j) {
+          if (labels[j] < 0) labels[j] = cid;
+        });
+      }
+      __syncthreads();
+      // their representatives are queried once each; core ones expand next
+      for (int64_t t = tid; t < (int64_t)nfront * 6; t += 1024) {
+        const uint64_t k = keys[6 * (int64_t)cur[t / 6] + t % 6];
+        if (k == 0) continue;
+        const int32_t r = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+        if (atomicExch(queried + r, 1) != 0) continue;
+        atomicAdd(&s_seeds, 1);
+        if (cnt[r] >= A.min_pts) nxt[atomicAdd(&s_next, 1)] = r;
+      }
+      __syncthreads();
+      nfront = s_next;
+      if (tid == 0) nq += s_seeds;
+      int32_t* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+      __syncthreads();
+    }
+  }
+  for (int32_t i = tid; i < n; i += 1024)
+    if (labels[i] == kFdbUnclassified) labels[i] = -1;
+  if (tid == 0) {
+    *nclusters = ncl;
+    if (nqueries) *nqueries = nq;
+  }
+}
+
 // ---- DM-SNR classification of clusters (Eqs. 3-4) ---------------------------
 // One 1024-thread workgroup per cluster.  LDS holds, per DM row, the count
 // and the largest SNR of the cluster's detections (an order-preserving int
@@ -477,6 +635,43 @@ hipError_t launch_cluster(const CandDev* c, int32_t n, int32_t ndms, int64_t t_e
     hipLaunchKernelGGL(cluster_rank_kernel, dim3(gn), dim3(256), 0, s, n, root, chunk, rank);
     hipLaunchKernelGGL(cluster_label_kernel, dim3(gn), dim3(256), 0, s, n, root, rank, labels);
   }
+  return hipGetLastError();
+}
+
+size_t fdbscan_work_bytes(int64_t n, int32_t ndms) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  return up(4 * (size_t)(ndms + 1)) + 4 * up(4 * (size_t)n) + up(48 * (size_t)n);
+}
+
+hipError_t launch_fdbscan(const CandDev* c, int32_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps, float snr_eps,
+                          int32_t min_pts, int32_t* labels, int32_t* nclusters, int64_t* nqueries, void* work,
+                          hipStream_t s) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  char* w = static_cast<char*>(work);
+  int32_t* row_start = reinterpret_cast<int32_t*>(w);
+  w += up(4 * (size_t)(ndms + 1));
+  int32_t* cnt = reinterpret_cast<int32_t*>(w);
+  w += up(4 * (size_t)n);
+  int32_t* queried = reinterpret_cast<int32_t*>(w);
+  w += up(4 * (size_t)n);
+  int32_t* fa = reinterpret_cast<int32_t*>(w);
+  w += up(4 * (size_t)n);
+  int32_t* fb = reinterpret_cast<int32_t*>(w);
+  w += up(4 * (size_t)n);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(w);
+  ClusterArgs A{c, n, ndms, dm_eps, t_eps, snr_eps, min_pts, row_start};
+  const unsigned gn = (unsigned)((n + 255) / 256);
+  const int64_t rows_threads = (int64_t)n * (2 * (int64_t)dm_eps + 1);
+  const unsigned gr = (unsigned)std::min<int64_t>((rows_threads + 255) / 256, int64_t(1) << 20);
+  hipLaunchKernelGGL(cluster_rows_kernel, dim3((unsigned)((ndms + 1 + 255) / 256)), dim3(256), 0, s, c, n, ndms,
+                     row_start);
+  if (n > 0) {
+    hipLaunchKernelGGL(fdb_init_kernel, dim3(gn), dim3(256), 0, s, n, cnt, keys, queried, labels);
+    hipLaunchKernelGGL(cluster_count_kernel, dim3(gr), dim3(256), 0, s, A, cnt);
+    hipLaunchKernelGGL(fdb_reps_kernel, dim3(gr), dim3(256), 0, s, A, cnt, keys);
+  }
+  hipLaunchKernelGGL(fdb_expand_kernel, dim3(1), dim3(1024), 0, s, A, cnt, keys, queried, fa, fb, labels, nclusters,
+                     nqueries);
   return hipGetLastError();
 }
 

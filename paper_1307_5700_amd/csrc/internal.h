@@ -246,6 +246,12 @@ inline size_t detect_work_bytes(int32_t ndms) {
   return align256(sizeof(int64_t) * 2 * kDetectSegs * size_t(ndms));
 }
 
+// FDBSCAN of detections (cluster.hip): workspace bytes and the launches.
+size_t fdbscan_work_bytes(int64_t n, int32_t ndms);
+hipError_t launch_fdbscan(const CandDev* c, int32_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps, float snr_eps,
+                          int32_t min_pts, int32_t* labels, int32_t* nclusters, int64_t* nqueries, void* work,
+                          hipStream_t s);
+
 // Most DM rows the allocation-free detection can take: its counts and
 // offsets live in a fixed device array of detect_work_bytes(this) = 2 MiB.
 constexpr int32_t kDetectNoAllocMaxDms = 8192;

@@ -852,6 +852,40 @@ mb_status cluster_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndm
   return ok();
 }
 
+mb_status fdbscan_workspace_size(int64_t n, int32_t ndms, size_t* bytes) {
+  if (!bytes) return fail(MB_EINVAL, "bytes must not be NULL");
+  if (n < 0 || n > 2147483647 - 1024) return fail(MB_EINVAL, "n must be in [0, 2^31 - 1024)");
+  if (ndms < 1 || ndms > kMaxDms) return fail(MB_EINVAL, "ndms must be in [1, %d]", kMaxDms);
+  *bytes = fdbscan_work_bytes(n, ndms);
+  return ok();
+}
+
+mb_status fdbscan_candidates(const mb_candidate* d_cands, int64_t n, int32_t ndms, int64_t t_eps, int32_t dm_eps,
+                             float snr_eps, int32_t min_pts, int32_t* d_labels, int32_t* d_nclusters,
+                             int64_t* d_nqueries, void* d_work, size_t work_bytes, void* stream) {
+  size_t need = 0;
+  mb_status st = fdbscan_workspace_size(n, ndms, &need);
+  if (st != MB_OK) return st;
+  if (t_eps < 0 || t_eps > 2147483647) return fail(MB_EINVAL, "t_eps must be in [0, 2^31)");
+  if (dm_eps < 0 || dm_eps > kMaxDms) return fail(MB_EINVAL, "dm_eps must be in [0, %d]", kMaxDms);
+  if (!(snr_eps >= 0.0f) || !isfinite(snr_eps)) return fail(MB_EINVAL, "snr_eps must be finite and >= 0");
+  if (min_pts < 1) return fail(MB_EINVAL, "min_pts must be >= 1");
+  if (!d_nclusters || !d_work) return fail(MB_EINVAL, "nclusters and work must not be NULL");
+  if (n > 0 && (!d_cands || !d_labels)) return fail(MB_EINVAL, "candidates and labels must not be NULL");
+  if (work_bytes < need) return fail(MB_EINVAL, "work is %zu bytes, %zu needed", work_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0) return fail(MB_EINVAL, "work must be 256-byte aligned");
+  if (d_nqueries && reinterpret_cast<uintptr_t>(d_nqueries) % 8 != 0)
+    return fail(MB_EINVAL, "nqueries must be 8-byte aligned");
+  const uintptr_t w0 = reinterpret_cast<uintptr_t>(d_work), w1 = w0 + need;
+  const uintptr_t l0 = reinterpret_cast<uintptr_t>(d_labels), l1 = l0 + 4 * (size_t)n;
+  const uintptr_t c0 = reinterpret_cast<uintptr_t>(d_cands), c1 = c0 + sizeof(mb_candidate) * (size_t)n;
+  if (n > 0 && ((l0 < w1 && w0 < l1) || (l0 < c1 && c0 < l1) || (c0 < w1 && w0 < c1)))
+    return fail(MB_EINVAL, "candidates, labels and work must not overlap");
+  HIP_TRY(launch_fdbscan(reinterpret_cast<const CandDev*>(d_cands), (int32_t)n, ndms, t_eps, dm_eps, snr_eps,
+                         min_pts, d_labels, d_nclusters, d_nqueries, d_work, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 // Defined with the clustering kernels (cluster.hip).
 extern "C++" {
 namespace mbtp {
