@@ -428,6 +428,56 @@ mb_status dedisp_batch_workspace_size(int32_t nitems, size_t* bytes);
 mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void* d_work,
                                size_t work_bytes, mb_exec_info* infos, void* stream);
 
+/* ---- captured chunk steps (HIP graphs) ---------------------------------- */
+
+/* One beam's chunk step for dedisp_step_graph_create: the RFI pass (when
+ * d_rfi_state is given), dedispersion with normalisation, and detection,
+ * with the arguments of rfi_threshold, dedisp_execute and
+ * detect_candidates.  All buffers are the caller's and must stay valid while
+ * the graph exists; each launch reads the current contents of d_in. */
+typedef struct {
+  const mb_plan* plan;
+  mb_beam* beam;              /* NULL: single shot; else in steady state     */
+  const void* d_in;
+  int64_t nsamps, ld;
+  void* d_rfi_state;          /* NULL: no RFI pass                           */
+  size_t rfi_state_bytes;
+  float* d_out;
+  int64_t ld_out;
+  mb_norm* d_norm;            /* required                                    */
+  double nsigma;
+  mb_candidate* d_cands;
+  int64_t capacity;
+  int64_t* d_count;
+  mb_peak* d_peaks;           /* nullable                                    */
+  void* d_detect_work;
+  size_t detect_work_bytes;
+} mb_step_item;
+
+typedef struct mb_step_graph mb_step_graph;
+
+/* Captures the chunk step of nitems beams (1..64) into one HIP graph on
+ * `stream` (not the null stream): every item's RFI pass, then one
+ * dedispersion of all items (dedisp_execute for a single item without
+ * d_batch_work, else dedisp_execute_batch with that workspace, Sec. 2's
+ * multibeam step), then every item's detection.  Nothing runs during the
+ * capture.  A streaming beam must be in steady state (it has seen at least
+ * its ring length R of samples, see dedisp_beam_create) and keeps the chunk
+ * length: the ring position and the detections' absolute samples are read
+ * on the device at run time, so every launch processes the next chunk of
+ * each beam.  The beams' host-side counts are left as they were.  Errors:
+ * MB_EINVAL (arguments, a beam not in steady state; nothing captured),
+ * MB_EDEVICE (capture or instantiation failed). */
+mb_status dedisp_step_graph_create(const mb_step_item* items, int32_t nitems, void* d_batch_work,
+                                   size_t batch_work_bytes, void* stream, mb_step_graph** out);
+/* Enqueues one replay on `stream` and advances every streaming beam's
+ * host-side count by its chunk length.  infos (nullable, host, [nitems])
+ * receives each item's nout and the absolute index of its first output.
+ * A beam must not be used by other calls between create and the last
+ * launch, except through launches of this graph. */
+mb_status dedisp_step_graph_launch(mb_step_graph* graph, void* stream, mb_exec_info* infos);
+mb_status dedisp_step_graph_destroy(mb_step_graph* graph);
+
 /* ---- streaming state --------------------------------------------------- */
 
 /* A beam's device-resident overlap ring: the last R cleaned FP32 samples of

@@ -58,6 +58,13 @@ class BatchItem(ctypes.Structure):
                 ("d_rfi_state", c_vp), ("d_out", c_vp), ("ld_out", c_i64), ("d_norm", c_vp)]
 
 
+class StepItem(ctypes.Structure):
+    _fields_ = [("plan", c_vp), ("beam", c_vp), ("d_in", c_vp), ("nsamps", c_i64), ("ld", c_i64),
+                ("d_rfi_state", c_vp), ("rfi_state_bytes", c_sz), ("d_out", c_vp), ("ld_out", c_i64),
+                ("d_norm", c_vp), ("nsigma", c_dbl), ("d_cands", c_vp), ("capacity", c_i64), ("d_count", c_vp),
+                ("d_peaks", c_vp), ("d_detect_work", c_vp), ("detect_work_bytes", c_sz)]
+
+
 class ExecInfo(ctypes.Structure):
     _fields_ = [("nout", c_i64), ("sample0", c_i64)]
 
@@ -110,6 +117,9 @@ _SIGS = {
                            c_vp, c_sz, c_vp], c_i32),
     "detect_candidates_noalloc": ([c_vp, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_dbl, c_vp, c_i64, c_vp,
                                    c_vp, c_vp], c_i32),
+    "dedisp_step_graph_create": ([ctypes.POINTER(StepItem), c_i32, c_vp, c_sz, c_vp, ctypes.POINTER(c_vp)], c_i32),
+    "dedisp_step_graph_launch": ([c_vp, c_vp, c_vp], c_i32),
+    "dedisp_step_graph_destroy": ([c_vp], c_i32),
     "mb_status_str": ([c_i32], ctypes.c_char_p),
     "mb_last_error": ([], ctypes.c_char_p),
 }

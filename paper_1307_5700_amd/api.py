@@ -528,18 +528,54 @@ class Beam:
             pass
 
 
+class _StepGraph:
+    """A chunk step captured by dedisp_step_graph_create (a HIP graph made by
+    the library) and replayed with dedisp_step_graph_launch."""
+
+    def __init__(self, items, work, stream):
+        n = len(items)
+        arr = (L.StepItem * n)(*items)
+        h = ctypes.c_void_p()
+        L.check(L.lib().dedisp_step_graph_create(arr, n, _ptr(work), work.numel() if work is not None else 0,
+                                                 _stream_ptr(stream), ctypes.byref(h)), "dedisp_step_graph_create")
+        self._h, self.n = h, n
+
+    def launch(self, stream=None):
+        infos = (L.ExecInfo * self.n)()
+        L.check(L.lib().dedisp_step_graph_launch(self._h, _stream_ptr(stream), infos), "dedisp_step_graph_launch")
+        return [(infos[i].nout, infos[i].sample0) for i in range(self.n)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and L._lib is not None:
+            L.lib().dedisp_step_graph_destroy(h)
+            self._h = None
+
+
+def _step_item(plan, x, state, out, norm, beam, nsigma, det):
+    T, ld = plan._check_input(x)
+    cands, count, peaks, work = det
+    return L.StepItem(plan._h, beam._h if beam is not None else None, x.data_ptr(), T, ld,
+                      state.data_ptr() if state is not None else None, state.numel() if state is not None else 0,
+                      out.data_ptr(), out.stride(0), norm.data_ptr(), float(nsigma), cands.data_ptr(),
+                      cands.numel() // L.CANDIDATE_BYTES, count.data_ptr(), peaks.data_ptr(), work.data_ptr(),
+                      work.numel())
+
+
 class ChunkGraph:
     """One chunk step captured as a HIP graph on fixed buffers and replayed.
 
     The step is the RFI pass (optional), dedispersion with normalisation and
-    detection, for one plan and an input buffer of fixed shape.  Before each
-    replay the caller writes the next chunk into ``x``; after it, ``out``,
-    ``norm`` and the detection buffers hold that chunk's results.
+    detection, for one plan and an input buffer of fixed shape; the library
+    captures it (dedisp_step_graph_create).  Before each replay the caller
+    writes the next chunk into ``x``; after it, ``out``, ``norm`` and the
+    detection buffers hold that chunk's results.
 
     With a beam, capture only once the beam is in steady state (it has seen
     at least one ring of samples, see include/mbtp.h) and keep the chunk
-    length fixed: the ring position is read on the device at run time, and
-    replay() keeps the beam's host-side sample count in step.
+    length fixed: the ring position and the triplets' absolute samples are
+    read on the device at run time, and each replay advances the beam's
+    host-side sample count.
     """
 
     def __init__(self, plan: Plan, x: torch.Tensor, rfi: bool = True, beam: "Beam | None" = None,
@@ -558,46 +594,29 @@ class ChunkGraph:
         self.norm = plan.alloc_norm()
         self.det = plan.alloc_detect(capacity)
         self.stream = torch.cuda.Stream(device=plan.device)
-        self.graph = torch.cuda.CUDAGraph()
         self.sample0 = None
-        self._first = True
         torch.cuda.synchronize(plan.device)
-        with torch.cuda.graph(self.graph, stream=self.stream):
-            self._enqueue()
-
-    def _enqueue(self):
-        p = self.plan
-        if self.state is not None:
-            p.rfi_threshold(self.x, self.state)
-        _, _, nout, s0 = p.execute(self.x, rfi_state=self.state, out=self.out, norm=self.norm,
-                                   beam=self.beam)
-        assert nout == self.nout
-        if self.beam is not None:
-            # the absolute sample is read on the device at every replay
-            p.detect(self.out, nout, self.norm, self.nsigma, buffers=self.det, beam=self.beam)
-        else:
-            p.detect(self.out, nout, self.norm, self.nsigma, sample0=s0, buffers=self.det)
-        self.sample0 = s0
+        item = _step_item(plan, x, self.state, self.out, self.norm, beam, nsigma, self.det)
+        self._graph = _StepGraph([item], None, self.stream)
 
     def replay(self):
-        """Runs the captured step on the current contents of ``x``; returns the
-        absolute index of the chunk's first output sample."""
-        if self.beam is not None and not self._first:
-            self.beam.advance(self.T)
-            self.sample0 += self.T
-        self._first = False
-        self.graph.replay()
-        return self.sample0
+        """Runs the captured step on the current contents of ``x`` (on the
+        current stream); returns the absolute index of the chunk's first
+        output sample."""
+        (_, s0), = self._graph.launch(torch.cuda.current_stream(self.plan.device))
+        self.sample0 = s0
+        return s0
 
 
 class BatchGraph:
     """The chunk step of several beams captured as one HIP graph.
 
     Per beam the RFI pass, then one batched persistent dedispersion launch
-    over every beam (with normalisation), then per beam detection.  All plans
-    must share the storage type and the tiling.  Capture once every beam is
-    in steady state (its ring is full); each replay then processes the
-    current contents of ``xs`` as the next chunk of every beam.
+    over every beam (with normalisation), then per beam detection, captured
+    by the library (dedisp_step_graph_create).  All plans must share the
+    storage type and the tiling.  Capture once every beam is in steady state
+    (its ring is full); each replay then processes the current contents of
+    ``xs`` as the next chunk of every beam.
     """
 
     def __init__(self, plans, xs, beams, rfi: bool = True, nsigma: float = 6.0,
@@ -618,27 +637,12 @@ class BatchGraph:
         self.dets = [p.alloc_detect(capacity) for p in plans]
         self.work = alloc_batch_work(len(plans), dev)
         self.stream = torch.cuda.Stream(device=dev)
-        self.graph = torch.cuda.CUDAGraph()
         self.sample0 = None
-        self._first = True
         torch.cuda.synchronize(dev)
-        with torch.cuda.graph(self.graph, stream=self.stream):
-            self._enqueue()
-
-    def _enqueue(self):
-        for p, x, st in zip(self.plans, self.xs, self.states):
-            if st is not None:
-                p.rfi_threshold(x, st)
-        jobs = [dict(plan=p, x=x, rfi_state=st, out=o, norm=n, beam=b)
-                for p, x, st, o, n, b in zip(self.plans, self.xs, self.states, self.outs,
-                                             self.norms, self.beams)]
-        res = execute_batch(jobs, work=self.work)
-        s0s = []
-        for p, (out, norm, nout, s0), det, b in zip(self.plans, res, self.dets, self.beams):
-            # the absolute sample is read on the device at every replay
-            p.detect(out, nout, norm, self.nsigma, buffers=det, beam=b)
-            s0s.append(s0)
-        self.sample0 = s0s
+        items = [_step_item(p, x, st, o, n, b, nsigma, d)
+                 for p, x, st, o, n, b, d in zip(self.plans, self.xs, self.states, self.outs, self.norms,
+                                                 self.beams, self.dets)]
+        self._graph = _StepGraph(items, self.work, self.stream)
 
     @property
     def dm_trial_samples(self) -> int:
@@ -646,11 +650,8 @@ class BatchGraph:
         return sum(p.ndms * T for p, T in zip(self.plans, self.T))
 
     def replay(self):
-        """Runs the captured step; returns each beam's first output sample."""
-        if not self._first:
-            for b, T in zip(self.beams, self.T):
-                b.advance(T)
-            self.sample0 = [s + T for s, T in zip(self.sample0, self.T)]
-        self._first = False
-        self.graph.replay()
+        """Runs the captured step (on the current stream); returns each
+        beam's first output sample."""
+        res = self._graph.launch(torch.cuda.current_stream(self.plans[0].device))
+        self.sample0 = [s0 for _, s0 in res]
         return list(self.sample0)

@@ -957,4 +957,121 @@ mb_status detect_candidates_noalloc(const mb_plan* plan, const float* d_out, int
   return ok();
 }
 
+struct mb_step_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Item { mb_beam* beam; int64_t nsamps, nout, sample0; };
+  std::vector<Item> items;
+};
+
+mb_status dedisp_step_graph_create(const mb_step_item* items, int32_t nitems, void* d_batch_work,
+                                   size_t batch_work_bytes, void* stream, mb_step_graph** out) {
+  if (!out) return fail(MB_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!items || nitems < 1 || nitems > 64) return fail(MB_EINVAL, "nitems must be in 1..64");
+  if (!stream) return fail(MB_EINVAL, "the null stream cannot be captured; pass a stream");
+  const bool batch = nitems > 1 || d_batch_work != nullptr;
+  for (int32_t i = 0; i < nitems; ++i) {
+    const mb_step_item& it = items[i];
+    if (!it.plan) return fail(MB_EINVAL, "item %d: plan is NULL", i);
+    if (!it.d_norm) return fail(MB_EINVAL, "item %d: the step needs d_norm", i);
+    if (it.beam) {
+      if (it.beam->plan != it.plan) return fail(MB_EINVAL, "item %d: beam was created from another plan", i);
+      if (it.beam->seen < it.beam->R)
+        return fail(MB_EINVAL, "item %d: the beam is not in steady state (%lld of %lld ring samples seen)", i,
+                    (long long)it.beam->seen, (long long)it.beam->R);
+      for (int32_t k = 0; k < i; ++k)
+        if (items[k].beam == it.beam) return fail(MB_EINVAL, "items %d and %d share a beam", k, i);
+    }
+  }
+  mb_step_graph* g = new (std::nothrow) mb_step_graph;
+  if (!g) return fail(MB_ENOMEM, "host allocation failed");
+  g->items.resize(nitems);
+  std::vector<int64_t> seen(nitems);
+  for (int32_t i = 0; i < nitems; ++i) seen[i] = items[i].beam ? items[i].beam->seen : 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(MB_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  mb_status st = MB_OK;
+  std::string why;
+  std::vector<mb_exec_info> infos(nitems);
+  for (int32_t i = 0; i < nitems && st == MB_OK; ++i) {
+    const mb_step_item& it = items[i];
+    if (it.d_rfi_state)
+      st = rfi_threshold(it.plan, it.d_in, it.nsamps, it.ld, it.d_rfi_state, it.rfi_state_bytes, stream);
+  }
+  if (st == MB_OK) {
+    if (!batch) {
+      const mb_step_item& it = items[0];
+      st = dedisp_execute(it.plan, it.beam, it.d_in, it.nsamps, it.ld, it.d_rfi_state, it.d_out, it.ld_out,
+                          it.d_norm, &infos[0], stream);
+    } else {
+      std::vector<mb_batch_item> bi(nitems);
+      for (int32_t i = 0; i < nitems; ++i) {
+        const mb_step_item& it = items[i];
+        bi[i] = mb_batch_item{it.plan, it.beam, it.d_in, it.nsamps, it.ld, it.d_rfi_state, it.d_out, it.ld_out,
+                              it.d_norm};
+      }
+      st = dedisp_execute_batch(bi.data(), nitems, d_batch_work, batch_work_bytes, infos.data(), stream);
+    }
+  }
+  for (int32_t i = 0; i < nitems && st == MB_OK; ++i) {
+    const mb_step_item& it = items[i];
+    const int64_t* d_s0 = it.beam ? it.beam->d_seen + 1 : nullptr;
+    st = detect_candidates(it.plan, it.d_out, infos[i].nout, it.ld_out, it.d_norm, it.beam ? 0 : infos[i].sample0,
+                           d_s0, it.nsigma, it.d_cands, it.capacity, it.d_count, it.d_peaks, it.d_detect_work,
+                           it.detect_work_bytes, stream);
+  }
+  if (st != MB_OK) why = g_err;
+  // the captured calls advanced the host counts of the beams; nothing ran
+  for (int32_t i = 0; i < nitems; ++i)
+    if (items[i].beam) items[i].beam->seen = seen[i];
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != MB_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    delete g;
+    if (st != MB_OK) return fail(st, "capturing the step: %s", why.c_str());
+    return fail(MB_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(MB_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  g->graph = graph;
+  for (int32_t i = 0; i < nitems; ++i)
+    g->items[i] = mb_step_graph::Item{items[i].beam, items[i].nsamps, infos[i].nout, infos[i].sample0};
+  *out = g;
+  return ok();
+}
+
+mb_status dedisp_step_graph_launch(mb_step_graph* graph, void* stream, mb_exec_info* infos) {
+  if (!graph) return fail(MB_EINVAL, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+  for (size_t i = 0; i < graph->items.size(); ++i) {
+    mb_step_graph::Item& it = graph->items[i];
+    int64_t s0 = it.sample0;
+    if (it.beam) {
+      // steady state: the first output lies s_max samples before the chunk
+      s0 = it.beam->base + it.beam->seen - it.beam->plan->smax;
+      it.beam->seen += it.nsamps;
+    }
+    if (infos) infos[i] = mb_exec_info{it.nout, s0};
+  }
+  return ok();
+}
+
+mb_status dedisp_step_graph_destroy(mb_step_graph* graph) {
+  if (!graph) return ok();
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return ok();
+}
+
 }  // extern "C"

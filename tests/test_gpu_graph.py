@@ -177,3 +177,26 @@ def test_batch_graph_replays_match_eager_batches():
             compare_candidates(gc, refs[i][k][1], refs[i][k][2])
         assert [b.position() for b in gb] == [b.position() for b in eb]
     assert all(sum(len(r[1]) for r in ref[1:]) > 0 for ref in refs)
+
+
+def test_step_graph_rejects_a_beam_before_steady_state_and_the_null_stream():
+    """dedisp_step_graph_create refuses, before capturing anything, a beam
+    whose ring is not yet full and the null stream; the beam's position is
+    left as it was."""
+    import ctypes
+    A = api()
+    b, s = _beam(8192)
+    plan = A.Plan.from_beam(b)
+    beam = A.Beam(plan)
+    xbuf = torch.zeros((512, 4096), dtype=torch.uint8, device="cuda")
+    with pytest.raises(A.L.MbError) as e:
+        A._StepGraph([A._step_item(plan, xbuf, None, plan.alloc_output(4096), plan.alloc_norm(), beam, 6.0,
+                                   plan.alloc_detect(16))], None, torch.cuda.Stream())
+    assert e.value.status == A.L.MB_EINVAL and "steady state" in str(e.value)
+    assert beam.position() == 0
+    item = A._step_item(plan, xbuf, None, plan.alloc_output(4096), plan.alloc_norm(), None, 6.0,
+                        plan.alloc_detect(16))
+    arr = (A.L.StepItem * 1)(item)
+    h = ctypes.c_void_p()
+    st = A.L.lib().dedisp_step_graph_create(arr, 1, None, 0, None, ctypes.byref(h))
+    assert st == A.L.MB_EINVAL and not h.value
