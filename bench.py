@@ -145,6 +145,7 @@ PMC_PASSES = [
     "GRBM_GUI_ACTIVE",
 ]
 SIMDS = 1024          # 256 CUs x 4 SIMDs
+XCDS = 8
 
 
 def pmc_summary(paths, workload: str) -> None:
@@ -179,11 +180,13 @@ def pmc_summary(paths, workload: str) -> None:
         out.append(f"{ctr}={v:.6g}    # {n} dispatches")
     g = lambda k: vals.get(k, (None,))[0]
     if g("SQ_ACTIVE_INST_VALU") and g("GRBM_GUI_ACTIVE"):
-        out.append(f"valu_busy_pct={100 * g('SQ_ACTIVE_INST_VALU') * 4 / SIMDS / g('GRBM_GUI_ACTIVE'):.1f}"
-                   "    # SQ_ACTIVE_INST_VALU x 4 / SIMDs / GRBM_GUI_ACTIVE")
+        # GRBM_GUI_ACTIVE is summed over the XCDs: per-XCD busy cycles are that / XCDS
+        out.append(f"gpu_cycles={g('GRBM_GUI_ACTIVE') / XCDS:.4g}    # GRBM_GUI_ACTIVE / {XCDS} XCDs")
+        out.append(f"valu_busy_pct={100 * g('SQ_ACTIVE_INST_VALU') * 4 / SIMDS / (g('GRBM_GUI_ACTIVE') / XCDS):.1f}"
+                   "    # SQ_ACTIVE_INST_VALU x 4 / SIMDs / gpu_cycles")
     if g("SQ_ACTIVE_INST_LDS") and g("GRBM_GUI_ACTIVE"):
-        out.append(f"lds_busy_pct={100 * g('SQ_ACTIVE_INST_LDS') * 4 / SIMDS / g('GRBM_GUI_ACTIVE'):.1f}"
-                   "    # SQ_ACTIVE_INST_LDS x 4 / SIMDs / GRBM_GUI_ACTIVE")
+        out.append(f"lds_busy_pct={100 * g('SQ_ACTIVE_INST_LDS') * 4 / SIMDS / (g('GRBM_GUI_ACTIVE') / XCDS):.1f}"
+                   "    # SQ_ACTIVE_INST_LDS x 4 / SIMDs / gpu_cycles")
     if g("SQ_INSTS_VALU"):
         out.append(f"valu_floor_ms={g('SQ_INSTS_VALU') * 4 / SIMDS / 2.4e9 * 1e3:.3f}"
                    "    # every VALU wave instruction 4 cycles on one of the SIMDs at 2.4 GHz")
