@@ -43,24 +43,40 @@ template <> struct Vec4Load<uint8_t> {
   static __device__ inline double one(const uint8_t* p) { return (double)*p; }
 };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// v of another lane by a DPP move of both halves: the source lane of
+// control CTRL in the rows of ROW_MASK, 0 where there is none.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_take(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, valid in lane 63: row
+// shifts by 1, 2, 4 and 8 leave each 16-lane row's sum in its last lane,
+// then the row broadcasts of lanes 15 and 31 carry rows 0-2 into row 3.
+__device__ inline double wave_total(double v) {
+  v += dpp_take<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_take<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_take<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_take<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_take<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
 // Block-wide FP64 sum over a 1024-thread block; fixed reduction tree.
 __device__ inline double block_sum_1024(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_total(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if (lane == 63) sh[w] = v;
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x < 64) {
     r = (lane < 16) ? sh[lane] : 0.0;
-    r = wave_sum(r);
-    if (lane == 0) sh[16] = r;
+    r = wave_total(r);
+    if (lane == 63) sh[16] = r;
   }
   __syncthreads();
   return sh[16];
@@ -96,8 +112,8 @@ __global__ __launch_bounds__(256) void rfi_stats_kernel(const TIN* __restrict__ 
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) col[i] += v[i];
-    double rs = wave_sum((v[0] + v[1]) + (v[2] + v[3]));
-    if (lane == 0) span_sum[c * nspans + span] = rs;
+    double rs = wave_total((v[0] + v[1]) + (v[2] + v[3]));
+    if (lane == 63) span_sum[c * nspans + span] = rs;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) col_sh[wave][4 * lane + i] = col[i];
@@ -126,8 +142,8 @@ __global__ __launch_bounds__(256) void rfi_chunks_kernel(const double* __restric
     chunk_sum[c * J + j] = m;
     part += m;
   }
-  part = wave_sum(part);
-  if (lane == 0) bsum[c] = part;
+  part = wave_total(part);
+  if (lane == 63) bsum[c] = part;
 }
 
 // ---------------------------------------------------------------------------
@@ -161,8 +177,8 @@ __device__ inline void block_sums_1024(const double (&v)[NV], double* sh /* 16*N
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    const double r = wave_sum(v[k]);
-    if (lane == 0) sh[w * NV + k] = r;
+    const double r = wave_total(v[k]);
+    if (lane == 63) sh[w * NV + k] = r;
   }
   __syncthreads();
   if (threadIdx.x < NV) {
