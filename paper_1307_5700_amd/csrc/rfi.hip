@@ -101,7 +101,26 @@ __global__ __launch_bounds__(256) void rfi_stats_kernel(const TIN* __restrict__ 
   const int64_t cb = (int64_t)g * CG, ce = min(C, cb + CG);
   const bool full = (tl + 3 < T);
   double col[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t c = cb + wave; c < ce; c += 4) {
+  int64_t c = cb + wave;
+  if (t0 + kSpan <= T) {
+    // (uniform: the whole span lies in the chunk, so every lane takes this
+    // path and the wave sums see the full wave) four of the wave's channels
+    // at a time, their loads in flight together; the sums take them in the
+    // same order as one at a time
+    for (; c + 12 < ce; c += 16) {
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Vec4Load<TIN>::load(x + (c + 4 * u) * ld + tl, v[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) col[i] += v[u][i];
+        const double rs = wave_total((v[u][0] + v[u][1]) + (v[u][2] + v[u][3]));
+        if (lane == 63) span_sum[(c + 4 * u) * nspans + span] = rs;
+      }
+    }
+  }
+  for (; c < ce; c += 4) {
     double v[4];
     const TIN* row = x + c * ld + tl;
     if (full) {
