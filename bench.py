@@ -47,6 +47,12 @@ PEAK_FP32_ADD_TFLOPS = 78.6     # 256 CUs x 128 FP32 lanes/clk x 2.4 GHz (adds o
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # MI355X vector FP32, an FMA counted as two flops
 
 
+def _progress(msg: str) -> None:
+    """A progress line of a long workload on stderr (stdout keeps the one
+    JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -612,6 +618,7 @@ def bench_serve(args):
                                      t_arrival=time.perf_counter()))
         srv.drain()
         srv.done.clear()
+        _progress(f"serve: {label} run, {len(beams)} beams x {n_per_beam} chunks")
         r = serve.poisson_run(srv, chunks(n_per_beam), beams[0].tsamp_s, speedup, seed=11)
         results[label] = r
         del srv
@@ -627,6 +634,7 @@ def bench_serve(args):
         L = int(rng.choice(lengths))
         blk = pool32[int(rng.integers(0, len(pool32)))]
         ch32.append(blk.view(-1)[:plan32.nchans * L].view(plan32.nchans, L))
+    _progress("serve: plain FP32 single-beam run")
     plain = serve.single_beam_run(plan32, ch32, beams[0].tsamp_s, 16.0, seed=11)
     del pool32, ch32
     cfg = {"workload": "served_stream_32beams_1024ch_640dm_u8", "chunks": "8192-65536 (Poisson)",
@@ -659,6 +667,7 @@ def bench_precision(args):
     nout = T - plan32.max_delay
     prow = [p.dm_index for p in base.pulses]
     rows = np.unique(np.concatenate([[0, plan32.ndms - 1], prow]))
+    _progress(f"precision: {C} x {T} plane rendered; FP64 oracle on {len(rows)} rows of the FP32 source")
     ref_src = oracle.dedisperse_rows(x32, s, rows, nout)           # FP64 on the FP32 source
 
     def err(D, ref):
@@ -691,6 +700,7 @@ def bench_precision(args):
         for p in base.pulses:
             i = int(np.searchsorted(rows, p.dm_index))
             snr.append(float(z[i, max(p.t0 - 2, 0):p.t0 + p.width + 2].max()))
+        _progress(f"precision: {dt_name} {dt * 1e3:.1f} ms per plane, error {e_max:.2e}, storage error {s_max:.2e}")
         per[dt_name] = {"ms": dt * 1e3, "value": plan.ndms * nout / dt,
                         "err_vs_fp64_oracle": e_max, "err_rms_vs_fp64_oracle": e_rms,
                         "storage_err_vs_f32_source": s_max, "storage_err_rms_vs_f32_source": s_rms,
