@@ -103,9 +103,11 @@ TRAFFIC = {
 }
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, workload: str) -> None:
+def traffic_summary(fetch_csv: str, write_csv: str, workload: str, last: int = 3) -> None:
     """HBM bytes per launch of the workload's kernel from the PMC runs, each
-    counter scaled by what it reads for the calibration copy of known size."""
+    counter scaled by what it reads for the calibration copy of known size:
+    the mean of the last `last` dispatches (the timed steps of the profiled
+    command, which takes --steps 3)."""
     import csv
     kname, fname, srcs, desc = TRAFFIC[workload]
 
@@ -126,8 +128,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, workload: str) -> None:
     # plan's small table upload is another)
     f_scale = CALIB_BYTES / float(np.max(f["copy"]))
     w_scale = CALIB_BYTES / float(np.max(w["copy"]))
-    fetch = float(np.mean(f["k"])) * f_scale
-    write = float(np.mean(w["k"])) * w_scale
+    fetch = float(np.mean(f["k"][-last:])) * f_scale
+    write = float(np.mean(w["k"][-last:])) * w_scale
     path = os.path.join(ROOT, "profiles", fname)
     wl = "" if workload == "paper" else f" --workload {workload}"
     with open(path, "w") as fh:
@@ -141,7 +143,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, workload: str) -> None:
         fh.write(f"kernel_source_hash={_kernel_hash(srcs)}\n")
         fh.write(f"# counter reading of the {CALIB_BYTES >> 20} MiB calibration copy, KiB: fetch "
                  f"{np.max(f['copy']) / 1024:.0f}, write {np.max(w['copy']) / 1024:.0f}\n")
-        fh.write(f"# {kname} dispatches: {len(f['k'])} (fetch), {len(w['k'])} (write)\n")
+        fh.write(f"# {kname} dispatches: {len(f['k'])} (fetch), {len(w['k'])} (write); the last {last} of each "
+                 "are the timed steps and are averaged\n")
         fh.write(f"fetch_scale={f_scale:.4f}\nwrite_scale={w_scale:.4f}\n")
         fh.write(f"fetch_bytes={fetch:.0f}\nwrite_bytes={write:.0f}\n")
         fh.write(f"bytes_per_launch={fetch + write:.0f}\n")
