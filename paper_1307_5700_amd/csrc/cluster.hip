@@ -1,5 +1,9 @@
-// DBSCAN clustering of detections in (time, DM, SNR) (Sec. 2.3), for gfx950.
+// Clustering of detections in (time, DM, SNR) (Sec. 2.3), for gfx950: the
+// exact DBSCAN below, the paper's FDBSCAN (expansion from representative
+// points in index order, further down), and the DM-SNR classification of
+// the clusters (Eqs. 3-4).
 //
+// DBSCAN:
 // The detections arrive in (DM index, sample) order, as the detection stage
 // writes them, so the neighbours of a point lie in the 2*dm_eps + 1 DM rows
 // around it, each a contiguous run of samples found by binary search.  A

@@ -131,6 +131,30 @@ def test_mask_rounds_match_oracle(passes):
     compare_candidates(g["cands"], r["cands"], r["z_margin"])
 
 
+@pytest.mark.parametrize("nchans,poly", [(4096, 3), (1536, 6), (512, 0)],
+                         ids=["4096ch_p3_global_fit", "1536ch_p6_global_fit", "512ch_p0_register_fit"])
+def test_fit_paths_match_oracle(nchans, poly):
+    """The bandpass fit runs in registers up to 2048 channels and degree 4,
+    and through global memory beyond: both against the oracle, with bursts
+    that need more than one mask round, spikes and a pulse."""
+    A = api()
+    f0, df = synth.band(nchans)
+    beam = synth.Beam(name="fit", nchans=nchans, f_ch0_mhz=f0, df_mhz=df, tsamp_s=51.2e-6, ndms=48,
+                      dm_start=0.0, dm_step=0.2, nsamps=4096, dtype="f32", seed=23,
+                      bursts=[synth.Burst(c0=nchans // 8, nch=4, t0=100, length=3000, amp=20.0),
+                              synth.Burst(c0=nchans // 2, nch=3, t0=2000, length=800, amp=20.0)],
+                      spikes=[synth.Spike(t0=3000, length=1, amp=20.0)], rfi=True)
+    beam.pulses = [synth.Pulse(dm_index=30, t0=1500, width=8, amp=1.0)]
+    x, s = beam_input(beam)
+    plan = A.Plan.from_beam(beam, rfi=A.RfiConfig(poly_order=poly))
+    g = run_gpu(plan, to_dev(x), rfi=True, nsigma=6.0)
+    r = oracle.run(x, oracle_plan(beam), rfi_params(plan.rfi_config), 6.0)
+    _check_rfi(g, r)
+    assert g["rfi"]["masked"][nchans // 8:nchans // 8 + 4].all()
+    assert err_sigma(g["D"], r["D"]) < TOL
+    compare_candidates(g["cands"], r["cands"], r["z_margin"])
+
+
 def test_paper_beam_full_plane():
     """1024 channels, 65536 samples, 640 DMs, RFI at 20 sigma, 5 sigma
     thresholds: every flag, every dedispersed sample and every candidate."""
