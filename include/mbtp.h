@@ -476,6 +476,8 @@ mb_status dedisp_step_graph_create(const mb_step_item* items, int32_t nitems, vo
  * A beam must not be used by other calls between create and the last
  * launch, except through launches of this graph. */
 mb_status dedisp_step_graph_launch(mb_step_graph* graph, void* stream, mb_exec_info* infos);
+/* Waits for the device to be idle (a launch may still be running), then
+ * frees the graph. */
 mb_status dedisp_step_graph_destroy(mb_step_graph* graph);
 
 /* ---- streaming state --------------------------------------------------- */

@@ -1068,9 +1068,12 @@ mb_status dedisp_step_graph_launch(mb_step_graph* graph, void* stream, mb_exec_i
 
 mb_status dedisp_step_graph_destroy(mb_step_graph* graph) {
   if (!graph) return ok();
+  // a launch may still be running on some stream: let it finish first
+  hipError_t e = hipDeviceSynchronize();
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
   delete graph;
+  if (e != hipSuccess) return fail(MB_EDEVICE, "hipDeviceSynchronize: %s", hipGetErrorString(e));
   return ok();
 }
 
