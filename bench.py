@@ -254,6 +254,8 @@ def stats_summary(paths, workload: str, steps: int) -> None:
            f"# then: python bench.py{wl} --steps {steps} --stats-from OUT/bench_kernel_stats.csv "
            "OUT/bench_kernel_trace.csv OUT/bench.json",
            f"kernel_source_hash={_kernel_hash(TRAFFIC[workload][2])}", "",
+           "# rocprofv3's statistics over every dispatch of the run (warm-up and, for the default workload, "
+           "its two-stream steps included)",
            f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'share':>6s}"]
     for r in rows[:14]:
         name = r["Name"] if len(r["Name"]) <= 70 else r["Name"][:67] + "..."
@@ -266,6 +268,17 @@ def stats_summary(paths, workload: str, steps: int) -> None:
     out += ["", f"{kname} per dispatch (us, in order): " + " ".join(f"{x:.1f}" for x in d),
             f"{kname} mean of the last {steps} dispatches (the timed steps): {np.mean(d[-steps:]):.1f} us; "
             f"grid {tr[-1]['Grid_Size_X']}, workgroup {tr[-1]['Workgroup_Size_X']}"]
+    # every kernel's mean over its last `steps` dispatches: the timed steps,
+    # one stream at a time (the default workload's two-stream steps, where
+    # kernels overlap and last longer, come before them)
+    by = {}
+    for r in sorted(csv.DictReader(open(paths[1])), key=lambda r: int(r["Start_Timestamp"])):
+        by.setdefault(_short_kernel_name(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out += ["", f"# mean of the last {steps} dispatches of each kernel (the timed one-stream steps), us"]
+    for k, dd in sorted(by.items()):
+        if len(dd) >= steps:
+            out.append(f"timed_us {k}={np.mean(dd[-steps:]):.2f}")
     if len(paths) > 2:
         lines = [l for l in open(paths[2]) if l.startswith("{")]
         ev = _event_kernel_ms(workload, json.loads(lines[-1]))
@@ -346,9 +359,19 @@ def _stream_kernel_bytes(C, T, N, nout, b, ngroups):
     }
 
 
+def _short_kernel_name(name: str) -> str:
+    """The function name of a demangled kernel name, without namespaces,
+    template arguments or parameters."""
+    n = name.replace("(anonymous namespace)", "")
+    for sep in ("<", "("):
+        n = n.split(sep, 1)[0]
+    return n.split("::")[-1].split()[-1]
+
+
 def _profiled_kernel_us(workload: str = "paper") -> dict:
-    """Average duration per dispatch of each kernel in the workload's
-    committed kernel trace, if it was taken on the current sources."""
+    """Duration per timed dispatch (the last ones, one stream at a time) of
+    each kernel in the workload's committed kernel trace, if it was taken on
+    the current sources."""
     fname, _ = STATS[workload]
     path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
@@ -359,13 +382,9 @@ def _profiled_kernel_us(workload: str = "paper") -> dict:
         return {}
     out = {}
     for l in lines:
-        parts = l.split()
-        if len(parts) >= 6 and parts[-1].endswith("%"):
-            name = l[:70]
-            for k in ("rfi_stats_kernel", "norm_kernel", "norm_finish_kernel", "detect_count_kernel",
-                      "dedisp_kernel", "rfi_fit_kernel"):
-                if f"{k}(" in name or f"{k}<" in name:
-                    out.setdefault(k, float(parts[-4]))
+        if l.startswith("timed_us "):
+            k, v = l[len("timed_us "):].split("=", 1)
+            out[k] = float(v)
     return out
 
 
