@@ -50,6 +50,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_ADD_TFLOPS = 78.6     # 256 CUs x 128 FP32 lanes/clk x 2.4 GHz (adds only)
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # MI355X vector FP32, an FMA counted as two flops
+PEAK_FP32_ADD_UNPACKED_TFLOPS = 39.3  # 256 CUs x 64 lanes/clk (a wave64 add holds a SIMD 4 cycles) x 2.4 GHz
 
 
 def _progress(msg: str) -> None:
@@ -519,6 +520,8 @@ def main():
                      "traffic": traffic,
                      "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
                      "published_fp32_tflops": PEAK_FP32_PUBLISHED_TFLOPS,
+                     "frac_of_unpacked_add_peak": achieved / PEAK_FP32_ADD_UNPACKED_TFLOPS,
+                     "unpacked_add_peak_tflops": PEAK_FP32_ADD_UNPACKED_TFLOPS,
                      "work": "C FP32 adds per DM-trial sample (each add one flop)"},
         "dedisp_hbm": {"algorithmic_bytes": kb["dedisp_kernel"], "algorithmic_gbs": dd_alg,
                        "algorithmic_pct_peak": 100 * dd_alg / PEAK_HBM_GBS,
