@@ -220,7 +220,12 @@ mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_
  * sample minus the fitted bandpass f_c rounded to FP32, or 0 where its chunk
  * or spectrum was flagged.
  * Sums are FP32, channels accumulated in ascending order in blocks of 32
- * (a fixed order, so results do not depend on the tiling).
+ * (a fixed order, so results do not depend on the tiling).  8-bit samples
+ * without cleaning sum to integers below 2^24, which FP32 holds exactly:
+ * such a chunk's outputs are the exact sums, whatever the tiling.  A
+ * single-shot (or first streamed) 8-bit chunk without cleaning, whose rows
+ * start 8-byte aligned with ld a multiple of 8, runs on an integer kernel
+ * (16-bit partial sums) that gives these same bits faster.
  *
  * beam == NULL: single shot over nsamps samples; nout = nsamps - s_max
  * outputs per DM (MB_EINVAL if nsamps <= s_max).

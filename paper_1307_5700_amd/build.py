@@ -27,6 +27,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
 SOURCES = {
     "rfi.hip": [],
     "dedisp.hip": [],
+    "dedisp_u8.hip": [],
     "detect.hip": [],
     "median.hip": [],
     "mulaw.hip": [],

@@ -31,6 +31,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "tile_map.h"
 
 namespace mbtp {
 namespace {
@@ -837,38 +838,10 @@ template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int
 __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int32_t* relb,
                                                          const float* fit32) {
   extern __shared__ float4 lds4[];
-  // Workgroup id -> tile.  Consecutive workgroups go to different XCDs; give
-  // each XCD a contiguous range of tiles, DM block fastest, so the blocks
-  // that share a time tile run on the same L2 at about the same time.  When
-  // the last DM block is partial (its idle consumers make its tiles
-  // cheaper), each XCD takes its share of the full blocks' tiles first and
-  // its share of the partial block's last, so the cheap tiles fill the
-  // final, partly occupied round.
   constexpr int BD = ((P & 8) ? NW - ((P & 64) ? 8 : 4) : NW) * G;
-  const int nd = A.n_dblocks, nt = A.n_ttiles;
-  const int ntile = nd * nt;
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, slot = bid >> 3;
-  const int q8 = ntile >> 3, rem = ntile & 7;
-  int dblock, ttile;
-  if (A.ndms % BD != 0 && nd > 1 && nt >= 8) {
-    const int nfull = (nd - 1) * nt;
-    const int f8 = nfull >> 3, frem = nfull & 7;
-    const int nf = f8 + (xcd < frem ? 1 : 0);            // full tiles of this XCD
-    const int fb = xcd * f8 + min(xcd, frem);            // first of them
-    if (slot < nf) {
-      dblock = (fb + slot) % (nd - 1);
-      ttile = (fb + slot) / (nd - 1);
-    } else {
-      dblock = nd - 1;
-      ttile = xcd * q8 + min(xcd, rem) - fb + (slot - nf);
-    }
-  } else {
-    const int tile = xcd * q8 + min(xcd, rem) + slot;
-    dblock = tile % nd;
-    ttile = tile / nd;
-  }
-  if (dblock >= nd || ttile >= nt) return;               // uniform: never taken
+  const TileIdx ti = xcd_tile(blockIdx.x, A.n_dblocks, A.n_ttiles, A.ndms % BD != 0);
+  const int dblock = ti.dblock, ttile = ti.ttile;
+  if (dblock >= A.n_dblocks || ttile >= A.n_ttiles) return;   // uniform: never taken
   dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P, true>(A, relb, fit32, reinterpret_cast<float*>(lds4),
                                                        dblock, ttile);
 }

@@ -185,6 +185,23 @@ hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs
 // workgroups per CU at `lds` bytes (occ[0] without, occ[1] with cleaning).
 hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]);
 
+// Integer kernel for 8-bit data without cleaning (dedisp_u8.hip): 12
+// consumer waves of kU8G DMs, kU8BT outputs per tile, kU8BC channels per
+// LDS stage staged as eight shifted 16-bit copies kU8RS samples apart, of
+// which a plan's rows use the first `rs` (a multiple of 8, at most kU8RS);
+// two stages of 160,256 bytes.
+constexpr int kU8G = 4, kU8BD = 48, kU8BT = 512, kU8BC = 4, kU8KM = 3, kU8RS = 1240;
+static_assert(kU8RS % 8 == 0 && kU8RS / 8 <= 64 * kU8KM, "integer staging rows");
+// Per-(DM, channel) LDS byte offsets of the integer kernel (ldr: table row
+// stride, channels rounded up to 4).
+hipError_t launch_relb_u8(const int32_t* delays, int32_t C, int32_t ndms, int32_t ldr, int32_t* relb,
+                          hipStream_t s);
+// Raises the integer kernel's LDS limit (at plan creation).
+hipError_t dedisp_u8_prepare();
+// One single-shot launch: a.rs, a.n_dblocks and a.n_ttiles in the integer
+// kernel's geometry; a.x 8-byte aligned with a.ld a multiple of 8.
+hipError_t launch_dedisp_u8(const DedispArgs& a, const int32_t* relb, size_t lds, hipStream_t s);
+
 // Writes the chunk's last min(L, R) cleaned samples into the ring at the
 // positions given by the beam's device-side sample count, then advances the
 // beam's device-side position (seen_dev: [seen, first output of the chunk,

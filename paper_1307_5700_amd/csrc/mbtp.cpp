@@ -97,6 +97,12 @@ struct mb_plan {
   int relb_ld = 0;
   int cus = 0;                 // compute units of the plan's device
   int batch_occ[2] = {1, 1};   // persistent workgroups per CU (no cleaning, cleaning)
+  // 8-bit plans: the exact integer kernel for chunks without cleaning, when
+  // its staging fits (copy length rs8 samples, lds8 bytes, offsets d_relb8)
+  bool u8_int = false;
+  int rs8 = 0;
+  size_t lds8 = 0;
+  int32_t* d_relb8 = nullptr;
 };
 
 struct mb_beam {
@@ -189,6 +195,18 @@ mb_status choose_tiling(mb_plan& p) {
   tiling_geometry(p, p.tiling, p.rs, p.lds);
   p.n_dblocks = (p.desc.ndms + p.tiling.BD() - 1) / p.tiling.BD();
   return MB_OK;
+}
+
+// Geometry of the integer kernel for 8-bit data: each staged copy holds the
+// largest window start (span + 7, rounded down to 8) plus the tile, plus the
+// octet after the last one read, whose successor the producers need.
+void u8_geometry(mb_plan& p) {
+  const int sp = span_max(p, kU8BD);
+  const int rs = ((sp + 7) & ~7) + kU8BT + 8;
+  const size_t lds = 2 * ((size_t)kU8BC * 16 * kU8RS + (size_t)kU8BC * kU8BD * sizeof(int32_t));
+  p.u8_int = p.desc.in_dtype == MB_U8 && rs <= kU8RS && lds <= kMaxLds;
+  p.rs8 = rs;
+  p.lds8 = lds;
 }
 
 mb_status validate_rfi(const mb_rfi_params& r, int C) {
@@ -285,13 +303,16 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
   }
   st = choose_tiling(*p);
   if (st) { delete p; return st; }
+  u8_geometry(*p);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return fail(MB_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)); }
   const size_t tb = sizeof(int32_t) * p->h_delays.size();
   p->relb_ld = (d.nchans + 3) & ~3;
   const size_t rb = sizeof(int32_t) * (size_t)p->relb_ld * d.ndms;
-  if (hipMalloc(&p->d_delays, tb) != hipSuccess || hipMalloc(&p->d_relb, rb) != hipSuccess) {
+  if (hipMalloc(&p->d_delays, tb) != hipSuccess || hipMalloc(&p->d_relb, rb) != hipSuccess ||
+      (p->u8_int && hipMalloc(&p->d_relb8, rb) != hipSuccess)) {
     (void)hipFree(p->d_delays);
+    (void)hipFree(p->d_relb);
     delete p;
     return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", tb + rb);
   }
@@ -300,6 +321,9 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
   if (e == hipSuccess) e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->tiling.copies(),
                                         p->relb_ld, p->d_relb, nullptr);
+  if (e == hipSuccess && p->u8_int) e = dedisp_u8_prepare();
+  if (e == hipSuccess && p->u8_int)
+    e = launch_relb_u8(p->d_delays, d.nchans, d.ndms, p->relb_ld, p->d_relb8, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   // the allocation-free detection's scratch address on this device, looked
   // up here so that later calls (possibly under graph capture) only read it
@@ -308,6 +332,7 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
   if (e != hipSuccess) {
     (void)hipFree(p->d_delays);
     (void)hipFree(p->d_relb);
+    (void)hipFree(p->d_relb8);
     delete p;
     return fail(MB_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
   }
@@ -319,6 +344,7 @@ mb_status dedisp_plan_destroy(mb_plan* plan) {
   if (!plan) return ok();
   (void)hipFree(plan->d_delays);
   (void)hipFree(plan->d_relb);
+  (void)hipFree(plan->d_relb8);
   delete plan;
   return ok();
 }
@@ -576,6 +602,14 @@ mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t 
   return MB_OK;
 }
 
+// Whether a prepared item runs on the exact integer kernel: 8-bit samples,
+// no cleaning, no ring samples staged, and rows the kernel can read as
+// aligned octets.  Its results equal the float kernels' bit for bit.
+bool uses_u8_int(const Prepared& P, bool ring) {
+  return P.plan->u8_int && !P.clean && !ring && P.a.phase == 0 &&
+         (reinterpret_cast<uintptr_t>(P.d_in) & 7) == 0 && P.ld % 8 == 0;
+}
+
 // Normalisation and ring update of a prepared item, after its dedispersion.
 mb_status finish_item(Prepared& P, hipStream_t s) {
   const mb_plan* plan = P.plan;
@@ -600,9 +634,17 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, i
   mb_status st = prepare(plan, beam, d_in, nsamps, ld, d_rfi_state, d_out, ld_out, d_norm, P);
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (P.nout > 0)
-    HIP_TRY(launch_dedisp(plan->desc.in_dtype, P.clean, beam != nullptr && P.a.ring_valid > 0, plan->tiling,
-                          P.a, plan->d_relb, P.fit32, plan->lds, s));
+  const bool ring = beam != nullptr && P.a.ring_valid > 0;
+  if (P.nout > 0 && uses_u8_int(P, ring)) {
+    DedispArgs a = P.a;
+    a.rs = plan->rs8;
+    a.n_dblocks = (plan->desc.ndms + kU8BD - 1) / kU8BD;
+    a.n_ttiles = (int32_t)((P.nout + kU8BT - 1) / kU8BT);
+    HIP_TRY(launch_dedisp_u8(a, plan->d_relb8, plan->lds8, s));
+  } else if (P.nout > 0) {
+    HIP_TRY(launch_dedisp(plan->desc.in_dtype, P.clean, ring, plan->tiling, P.a, plan->d_relb, P.fit32,
+                          plan->lds, s));
+  }
   st = finish_item(P, s);
   if (st) return st;
   if (info) {

@@ -185,14 +185,15 @@ def test_paper_beam_full_plane():
 @pytest.mark.parametrize("dtype", ["f32", "u8"])
 def test_tiling_does_not_change_a_bit_without_rfi(dtype):
     """Without the RFI pass, every compiled tiling gives the same bits too
-    (the uncleaned staging paths, FP32 and uint8)."""
+    (the uncleaned staging paths, FP32 and uint8).  The uint8 rows have a
+    stride of 4 mod 8, which keeps them off the integer kernel."""
     A = api()
     beam = synth.paper_beam(dtype=dtype, nsamps=16384)
     beam.ndms = 200
     beam.rfi = False
     beam.pulses = [p for p in beam.pulses if p.dm_index < 200]
     x, _ = beam_input(beam)
-    xd = to_dev(x)
+    xd = to_dev(x, 16384 + 4)
     ref = None
     used = set()
     for hint in range(1, A.num_tilings() + 1):

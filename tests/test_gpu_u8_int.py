@@ -1,0 +1,88 @@
+"""The exact integer kernel for 8-bit filterbanks without cleaning
+(Sec. 2.2.2).  Sums of 8-bit samples are integers below 2^24, so the FP32
+output equals the FP64 oracle's sum exactly, and equals the float kernels'
+output (whose partial sums of 8-bit data are exact integers too) bit for
+bit.  Rows whose stride is a multiple of 8 from an 8-byte aligned base take
+the integer kernel; a stride of 4 mod 8 takes a float kernel.  (The
+4096-channel, 2048-DM, 262144-sample 8-bit plane runs on it in
+test_gpu_fullsize, exact on sampled rows.)"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1307_5700_amd import synth
+
+from gpu_util import api, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _beam(C, nd, T, dm_step=0.2, tsamp=51.2e-6, seed=5):
+    f0, df = synth.band(C)
+    b = synth.Beam(name=f"u8int{C}", nchans=C, f_ch0_mhz=f0, df_mhz=df, tsamp_s=tsamp, ndms=nd,
+                   dm_start=0.0, dm_step=dm_step, nsamps=T, dtype="u8", seed=seed)
+    s = oracle.delay_table(**b.plan_kwargs())
+    b.pulses = [synth.Pulse(dm_index=nd // 2, t0=T // 3, width=4, amp=1.0)]
+    return b, s
+
+
+def _run(plan, x, ld):
+    xd = to_dev(x, ld)
+    assert xd.stride(0) == ld
+    out, _, nout, _ = plan.execute(xd)
+    torch.cuda.synchronize()
+    return out[:, :nout].cpu().numpy(), nout
+
+
+# (channels, DMs, samples): 16-bit partials widened at 256 channels (C above
+# 256, not a multiple of 256 or of 4), a partial last DM block (DMs not a
+# multiple of 48), ragged last time tiles, a single partial tile, a single
+# channel and a single DM.
+SHAPES = [(256, 64, 8192), (300, 100, 12000), (1024, 97, 16384), (517, 48, 9000), (1, 1, 600),
+          (64, 49, 1200), (2048, 130, 20000)]
+
+
+@pytest.mark.parametrize("C,nd,T", SHAPES, ids=[f"{c}ch_{d}dm_{t}" for c, d, t in SHAPES])
+def test_integer_kernel_equals_oracle_and_float_kernel(C, nd, T):
+    A = api()
+    b, s = _beam(C, nd, T)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    ref = oracle.dedisperse(x, s)
+    D8, nout = _run(plan, x, (T + 7) // 8 * 8)            # integer kernel
+    assert nout == ref.shape[1]
+    assert np.array_equal(D8, ref.astype(np.float32))    # exact: integer sums below 2^24
+    Df, _ = _run(plan, x, (T + 7) // 8 * 8 + 4)           # float kernel (stride 4 mod 8)
+    assert np.array_equal(Df, D8)
+
+
+def test_integer_kernel_with_saturated_samples():
+    """All-255 input: every 16-bit partial reaches 256 * 255 = 65280 before
+    it is widened, and the totals C * 255 for every output."""
+    A = api()
+    b, s = _beam(1024, 96, 8192)
+    x = np.full((1024, 8192), 255, dtype=np.uint8)
+    plan = A.Plan.from_beam(b)
+    D, nout = _run(plan, x, 8192)
+    assert nout == 8192 - int(s.max())
+    assert np.all(D == np.float32(1024 * 255))
+
+
+def test_integer_kernel_first_chunk_of_a_stream_equals_single_shot():
+    """A stream's first chunk stages no ring samples and runs on the integer
+    kernel; later chunks run on the float ring kernel.  The stream's outputs
+    equal a single shot over the concatenated chunks, bit for bit."""
+    A = api()
+    T = 4096 * 3
+    b, s = _beam(512, 96, T)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    beam = A.Beam(plan)
+    outs = []
+    for k in range(3):
+        out, _, nout, s0 = plan.execute(to_dev(x[:, k * 4096:(k + 1) * 4096], 4096), beam=beam)
+        outs.append(out[:, :nout].cpu().numpy())
+    single, nout = _run(plan, x, T)
+    assert np.array_equal(np.concatenate(outs, axis=1), single)
+
