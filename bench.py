@@ -91,7 +91,7 @@ CALIB_BYTES = 256 * 1024 * 1024
 # Kernels whose HBM traffic is summarised under profiles/: workload ->
 # (kernel name substring, summary file, sources hashed, description).
 TRAFFIC = {
-    "paper": ("dedisp_kernel", "dedisp_traffic.txt", ("dedisp.hip", "rfi.hip", "detect.hip", "internal.h"),
+    "paper": ("dedisp_kernel", "dedisp_traffic.txt", ("dedisp.hip", "tile_map.h", "rfi.hip", "detect.hip", "internal.h"),
               "one dedisp_kernel launch, bench workload (1024 ch x 65536 samples x 640 DMs, f32, RFI on)"),
     "median": ("median_kernel<2>", "median_traffic.txt", ("median.hip", "internal.h"),
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
