@@ -99,6 +99,9 @@ typedef struct {
   int32_t tile_index;   /* 1-based index of the compiled tiling in use    */
   int32_t waves;        /* wave64s per dedispersion workgroup             */
   int64_t lds_bytes;    /* LDS per dedispersion workgroup                 */
+  int32_t u8_integer;   /* 1: 8-bit chunks without cleaning can run on the
+                           exact integer kernel (see dedisp_execute)       */
+  int32_t reserved;
 } mb_plan_info;
 
 /* Summary of one RFI pass, read back with rfi_report(). */
@@ -159,6 +162,8 @@ typedef struct {
 typedef struct {
   int64_t nout;      /* dedispersed samples produced per DM by this call   */
   int64_t sample0;   /* absolute index of the first of them                */
+  int32_t integer_kernel; /* 1 when the exact integer kernel dedispersed it */
+  int32_t reserved;
 } mb_exec_info;
 
 typedef struct mb_plan mb_plan;

@@ -37,7 +37,7 @@ class PlanDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("nchans", c_i32), ("ndms", c_i32), ("max_delay", c_i32), ("dm_block", c_i32),
                 ("time_tile", c_i32), ("chan_block", c_i32), ("tile_index", c_i32), ("waves", c_i32),
-                ("lds_bytes", c_i64)]
+                ("lds_bytes", c_i64), ("u8_integer", c_i32), ("reserved", c_i32)]
 
 
 class RfiReport(ctypes.Structure):
@@ -66,7 +66,7 @@ class StepItem(ctypes.Structure):
 
 
 class ExecInfo(ctypes.Structure):
-    _fields_ = [("nout", c_i64), ("sample0", c_i64)]
+    _fields_ = [("nout", c_i64), ("sample0", c_i64), ("integer_kernel", c_i32), ("reserved", c_i32)]
 
 
 DETECT_NOALLOC_MAX_DMS = 8192   # MB_DETECT_NOALLOC_MAX_DMS

@@ -78,7 +78,8 @@ class Plan:
         self.max_delay = info.max_delay
         self.tiling = dict(index=info.tile_index, waves=info.waves, dm_block=info.dm_block,
                            time_tile=info.time_tile, chan_block=info.chan_block,
-                           lds_bytes=info.lds_bytes)
+                           lds_bytes=info.lds_bytes, u8_integer=bool(info.u8_integer))
+        self.last_integer_kernel = False   # whether the last execute ran the exact integer kernel
         self.dm_start, self.dm_step = float(dm_start), float(dm_step)
         ws = ctypes.c_size_t()
         L.check(L.lib().detect_workspace_size(h, ctypes.byref(ws)), "detect_workspace_size")
@@ -193,6 +194,7 @@ class Plan:
             median_filter(raw, info.nout, median, out=out, stream=stream)
             if norm is not None:
                 self.normalise(out, info.nout, norm, stream=stream)
+        self.last_integer_kernel = bool(info.integer_kernel)
         return out, norm, info.nout, info.sample0
 
     def normalise(self, out: torch.Tensor, nout: int, norm: torch.Tensor | None = None, stream=None):

@@ -360,6 +360,8 @@ mb_status dedisp_plan_info(const mb_plan* plan, mb_plan_info* info) {
   info->tile_index = plan->tile_index;
   info->waves = plan->tiling.NW;
   info->lds_bytes = (int64_t)plan->lds;
+  info->u8_integer = plan->u8_int ? 1 : 0;
+  info->reserved = 0;
   return ok();
 }
 
@@ -635,7 +637,8 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, i
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool ring = beam != nullptr && P.a.ring_valid > 0;
-  if (P.nout > 0 && uses_u8_int(P, ring)) {
+  const bool integer = P.nout > 0 && uses_u8_int(P, ring);
+  if (integer) {
     DedispArgs a = P.a;
     a.rs = plan->rs8;
     a.n_dblocks = (plan->desc.ndms + kU8BD - 1) / kU8BD;
@@ -650,6 +653,8 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, i
   if (info) {
     info->nout = P.nout;
     info->sample0 = P.sample0;
+    info->integer_kernel = integer ? 1 : 0;
+    info->reserved = 0;
   }
   return ok();
 }
@@ -724,6 +729,8 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
     if (infos) {
       infos[i].nout = P[i].nout;
       infos[i].sample0 = P[i].sample0;
+      infos[i].integer_kernel = 0;
+      infos[i].reserved = 0;
     }
   }
   return ok();
@@ -1002,7 +1009,7 @@ mb_status detect_candidates_noalloc(const mb_plan* plan, const float* d_out, int
 struct mb_step_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  struct Item { mb_beam* beam; int64_t nsamps, nout, sample0; };
+  struct Item { mb_beam* beam; int64_t nsamps, nout, sample0; int32_t integer_kernel; };
   std::vector<Item> items;
 };
 
@@ -1087,7 +1094,8 @@ mb_status dedisp_step_graph_create(const mb_step_item* items, int32_t nitems, vo
   }
   g->graph = graph;
   for (int32_t i = 0; i < nitems; ++i)
-    g->items[i] = mb_step_graph::Item{items[i].beam, items[i].nsamps, infos[i].nout, infos[i].sample0};
+    g->items[i] = mb_step_graph::Item{items[i].beam, items[i].nsamps, infos[i].nout, infos[i].sample0,
+                                      infos[i].integer_kernel};
   *out = g;
   return ok();
 }
@@ -1103,7 +1111,7 @@ mb_status dedisp_step_graph_launch(mb_step_graph* graph, void* stream, mb_exec_i
       s0 = it.beam->base + it.beam->seen - it.beam->plan->smax;
       it.beam->seen += it.nsamps;
     }
-    if (infos) infos[i] = mb_exec_info{it.nout, s0};
+    if (infos) infos[i] = mb_exec_info{it.nout, s0, it.integer_kernel, 0};
   }
   return ok();
 }

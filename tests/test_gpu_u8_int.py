@@ -27,11 +27,13 @@ def _beam(C, nd, T, dm_step=0.2, tsamp=51.2e-6, seed=5):
     return b, s
 
 
-def _run(plan, x, ld):
+def _run(plan, x, ld, integer=None):
     xd = to_dev(x, ld)
     assert xd.stride(0) == ld
     out, _, nout, _ = plan.execute(xd)
     torch.cuda.synchronize()
+    if integer is not None:
+        assert plan.last_integer_kernel == integer
     return out[:, :nout].cpu().numpy(), nout
 
 
@@ -49,11 +51,12 @@ def test_integer_kernel_equals_oracle_and_float_kernel(C, nd, T):
     b, s = _beam(C, nd, T)
     x = synth.render(b, s)
     plan = A.Plan.from_beam(b)
+    assert plan.tiling["u8_integer"]
     ref = oracle.dedisperse(x, s)
-    D8, nout = _run(plan, x, (T + 7) // 8 * 8)            # integer kernel
+    D8, nout = _run(plan, x, (T + 7) // 8 * 8, integer=True)
     assert nout == ref.shape[1]
     assert np.array_equal(D8, ref.astype(np.float32))    # exact: integer sums below 2^24
-    Df, _ = _run(plan, x, (T + 7) // 8 * 8 + 4)           # float kernel (stride 4 mod 8)
+    Df, _ = _run(plan, x, (T + 7) // 8 * 8 + 4, integer=False)   # stride 4 mod 8
     assert np.array_equal(Df, D8)
 
 
@@ -64,7 +67,7 @@ def test_integer_kernel_with_saturated_samples():
     b, s = _beam(1024, 96, 8192)
     x = np.full((1024, 8192), 255, dtype=np.uint8)
     plan = A.Plan.from_beam(b)
-    D, nout = _run(plan, x, 8192)
+    D, nout = _run(plan, x, 8192, integer=True)
     assert nout == 8192 - int(s.max())
     assert np.all(D == np.float32(1024 * 255))
 
@@ -82,7 +85,34 @@ def test_integer_kernel_first_chunk_of_a_stream_equals_single_shot():
     outs = []
     for k in range(3):
         out, _, nout, s0 = plan.execute(to_dev(x[:, k * 4096:(k + 1) * 4096], 4096), beam=beam)
+        assert plan.last_integer_kernel == (k == 0)
         outs.append(out[:, :nout].cpu().numpy())
-    single, nout = _run(plan, x, T)
+    single, nout = _run(plan, x, T, integer=True)
     assert np.array_equal(np.concatenate(outs, axis=1), single)
 
+
+
+def test_cleaning_and_other_storage_types_take_the_float_kernels():
+    """With an RFI state, or in f16/f32, the integer kernel never runs; a
+    plan whose staged rows exceed its copy length reports it cannot."""
+    A = api()
+    b, s = _beam(512, 96, 8192)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    xd = to_dev(x, 8192)
+    plan.execute(xd, rfi_state=plan.rfi_threshold(xd))
+    assert not plan.last_integer_kernel
+    for dt in ("f16", "f32"):
+        bf, _ = _beam(512, 96, 8192)
+        bf.dtype = dt
+        p = A.Plan.from_beam(bf)
+        assert not p.tiling["u8_integer"]
+        p.execute(to_dev(synth.quantise(np.asarray(x, np.float32), dt), 8192))
+        assert not p.last_integer_kernel
+    # a coarse DM step: 48 DMs span more than the copy length
+    bc, sc = _beam(512, 96, 30000, dm_step=2.0)
+    pc = A.Plan.from_beam(bc)
+    assert not pc.tiling["u8_integer"]
+    xc = synth.render(bc, sc)
+    D, nout = _run(pc, xc, 30000, integer=False)
+    assert np.array_equal(D, oracle.dedisperse(xc, sc).astype(np.float32))
