@@ -65,8 +65,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "precision", "median", "mulaw",
-                                                             "power", "cluster"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "paper_u8", "batch", "serve", "precision",
+                                                             "median", "mulaw", "power", "cluster"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline sample")
     ap.add_argument("--calib-copy", action="store_true",
@@ -93,6 +93,8 @@ CALIB_BYTES = 256 * 1024 * 1024
 TRAFFIC = {
     "paper": ("dedisp_kernel", "dedisp_traffic.txt", ("dedisp.hip", "tile_map.h", "rfi.hip", "detect.hip", "internal.h"),
               "one dedisp_kernel launch, bench workload (1024 ch x 65536 samples x 640 DMs, f32, RFI on)"),
+    "paper_u8": ("dedisp_u8_kernel", "dedisp_u8_traffic.txt", ("dedisp_u8.hip", "tile_map.h", "internal.h"),
+                 "one dedisp_u8_kernel launch, paper_u8 workload (1024 ch x 65536 u8 samples x 640 DMs, no RFI)"),
     "median": ("median_kernel<2>", "median_traffic.txt", ("median.hip", "internal.h"),
                "one median_kernel<2> launch, median workload (640 DMs x 59434 outputs, f32, half width 2)"),
     "mulaw": ("mulaw_encode_kernel", "mulaw_traffic.txt", ("mulaw.hip", "internal.h"),
@@ -214,6 +216,8 @@ def pmc_summary(paths, workload: str) -> None:
 STATS = {
     "paper": ("paper_beam_f32_rfi_kernel_stats.txt",
               "kernel trace of the default workload (1024 ch x 65536 f32 samples x 640 DMs, RFI on)"),
+    "paper_u8": ("paper_beam_u8_kernel_stats.txt",
+                 "kernel trace of the paper_u8 workload (1024 ch x 65536 u8 samples x 640 DMs, no RFI)"),
     "median": ("median_640dm_59434samp_kernel_stats.txt",
                "kernel trace of the median workload (640 DMs x 59434 f32 outputs; h = 2, 1, 4, 8, 16)"),
     "mulaw": ("mulaw_1024ch_65536samp_kernel_stats.txt",
@@ -233,7 +237,7 @@ def _event_kernel_ms(workload: str, res: dict):
         return res["half_widths"]["2"]["kernel_ms"]
     if workload == "mulaw":
         return res["encode_kernel_ms"]
-    if workload in ("power", "cluster"):
+    if workload in ("power", "cluster", "paper_u8"):
         return res["kernel_ms"]
     return None
 
@@ -407,7 +411,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     if args.workload != "paper":
-        res = {"batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
+        res = {"paper_u8": bench_paper_u8, "batch": bench_batch, "serve": bench_serve, "precision": bench_precision,
                "median": bench_median, "mulaw": bench_mulaw, "power": bench_power,
                "cluster": bench_cluster}[args.workload](args)
         print(json.dumps(res), flush=True)
@@ -562,6 +566,82 @@ def _line(metric_value, dt, args, dtype, config, extra):
            "data": "synthetic", "config": config}
     res.update(extra)
     return res
+
+
+PEAK_U16X2_ADD_TOPS = 78.6   # 256 CUs x 64 lanes/clk x 2 adds per v_pk_add_u16 x 2.4 GHz
+
+
+def bench_paper_u8(args):
+    """The paper-shaped beam stored in 8 bits (1024 ch x 65536 samples x 640
+    DMs, mean 128 and std 16 per sample), without the RFI pass: dedispersion
+    on the exact integer kernel, normalisation and detection.  One step = one
+    chunk.  HIP events on the stream time the dedispersion launch, on these
+    rows and on the same data with a row stride of 4 mod 8, which runs the
+    float kernel (the same bits)."""
+    import torch
+    from paper_1307_5700_amd import api as A
+    from paper_1307_5700_amd import synth
+    beam = synth.paper_beam(dtype="u8")
+    plan = A.Plan.from_beam(beam)
+    xh = synth.render(beam, plan.delays())
+    C, T = xh.shape
+    x = torch.from_numpy(xh).cuda()
+    wide = torch.zeros((C, T + 4), dtype=torch.uint8, device="cuda")
+    wide[:, :T] = x
+    nout = T - plan.max_delay
+    out, norm, det = plan.alloc_output(nout), plan.alloc_norm(), plan.alloc_detect(1 << 16)
+
+    def step():
+        plan.execute(x, out=out, norm=norm)
+        plan.detect(out, nout, norm, beam.nsigma, buffers=det)
+    dt = _timed(step, args.steps, args.warmup)
+    ncand = int(det[1].item())
+    stream = torch.cuda.current_stream()
+
+    def kernel_ms(xx):
+        for _ in range(args.warmup):
+            plan.execute(xx, out=out, norm=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.execute(xx, out=out, norm=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, plan.last_integer_kernel
+    k_int, used_int = kernel_ms(x)
+    k_flt, used_flt = kernel_ms(wide[:, :T])
+    if not used_int or used_flt:
+        raise RuntimeError("the 8-bit rows did not take the expected kernels")
+    _progress(f"paper_u8: step {dt * 1e3:.3f} ms, integer kernel {k_int:.3f} ms, float kernel {k_flt:.3f} ms")
+    adds = C * plan.ndms * nout
+    achieved = adds / (k_int * 1e-3) / 1e12
+    lds_read = plan.ndms * nout * C * 2            # one 16-bit term per add
+    cfg = {"workload": "paper_beam_1024ch_65536samp_640dm_u8", "nchans": C, "nsamps": T, "ndms": plan.ndms,
+           "nout": nout, "rfi": "off", "nsigma": beam.nsigma, "parallelism": "none"}
+    extra = {"candidates": ncand, "kernel_ms": k_int, "float_kernel_ms": k_flt,
+             "speedup_vs_float_kernel": k_flt / k_int,
+             "roofline": {"bound": "alu", "kernel": "dedisp_u8_kernel", "achieved": achieved,
+                          "peak": PEAK_U16X2_ADD_TOPS, "unit": "TOP/s", "frac": achieved / PEAK_U16X2_ADD_TOPS,
+                          "traffic": _traffic("paper_u8"),
+                          "work": "C 16-bit integer adds per DM-trial sample, two per v_pk_add_u16",
+                          "lds_read_gbs": lds_read / (k_int * 1e-3) / 1e9}}
+    if not args.no_cpu_baseline:
+        import oracle
+        pd = oracle.PlanDesc(**beam.plan_kwargs())
+        reps, t_total = 0, 0.0
+        while reps < 8 and (t_total < args.cpu_seconds or reps == 0):
+            t0 = time.perf_counter()
+            oracle.run(xh, pd, None, beam.nsigma)
+            t_total += time.perf_counter() - t0
+            reps += 1
+        extra["cpu_baseline"] = {"value": plan.ndms * nout * reps / t_total, "unit": "DM-trial samples/s",
+                                 "cores": oracle.max_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+                                 "sample": f"{reps} full steps of the same chunk (dedispersion, normalisation, "
+                                           f"detection; no RFI pass) in {t_total:.1f} s"}
+    if args.calib_copy:
+        _calib_copy()
+    return _line(plan.ndms * nout / dt, dt, args, "u8", cfg, extra)
 
 
 def bench_batch(args):
