@@ -130,15 +130,21 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
 
   if (wave < kProd) {
     // ---- producer: stages row `wave` of every block ----
-    const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;   // DM d0's delays
+    const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;      // DM d0's delays
+    const int32_t* __restrict__ dz = A.delays + (int64_t)dlast * C;   // the block's last DM's
     const int vz = lane * A.zero;                  // 0, but lane-dependent: vector loads
     uint2 raw[kPF][kU8KM];                         // kPF blocks of loads in flight
     int offreg[kPF];
-    // s[d0][c] of each set's next row, loaded kPF blocks before it is used,
-    // so that waiting for it waits only for loads already consumed
-    int basen[kPF];
+    int nwr[kPF];                                  // octets written of each set's row
+    // s[d0][c] and s[dlast][c] of each set's next row, loaded kPF blocks
+    // before they are used, so that waiting for them waits only for loads
+    // already consumed
+    int basen[kPF], lastn[kPF];
 #pragma unroll
-    for (int j = 0; j < kPF; ++j) basen[j] = dl[min(j * kU8BC + wave, C - 1) + vz];
+    for (int j = 0; j < kPF; ++j) {
+      basen[j] = dl[min(j * kU8BC + wave, C - 1) + vz];
+      lastn[j] = dz[min(j * kU8BC + wave, C - 1) + vz];
+    }
 
     // Issues the loads of the block starting at channel cb0 into set S.
     // Every call issues the same loads whatever the block (rows past the
@@ -148,18 +154,28 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
     auto issue = [&](int cb0, auto set_c) {
       constexpr int S = decltype(set_c)::value;
       const int base = __builtin_amdgcn_readfirstlane(basen[S]);
+      const int last = __builtin_amdgcn_readfirstlane(lastn[S]);
       basen[S] = dl[min(cb0 + kPF * kU8BC + wave, C - 1) + vz];
+      lastn[S] = dz[min(cb0 + kPF * kU8BC + wave, C - 1) + vz];
       const int c = min(cb0 + wave, C - 1);
       const int32_t a = t0 + (base & ~7);          // chunk index of the row's first staged sample
+      // The block's windows in this row start at most (s[dlast][c] - a) & ~7
+      // positions in (delays grow with DM), so its consumers read the first
+      // that / 8 + 64 octets of each copy; the copies of the last of them
+      // take samples from the octet after it.  A row near the top of the
+      // band, where the delay spread is small, stages only that much.
+      const int nw = min(((last - (base & ~7)) >> 3) + 64, nocts);
+      nwr[S] = nw;
       const uint8_t* xrow = static_cast<const uint8_t*>(A.x) + (int64_t)c * A.ld;
 #pragma unroll
       for (int k = 0; k < kU8KM; ++k) {
         const int m = lane + 64 * k;
         const int32_t off = a + 8 * m;
         // the octet holding a chunk sample lies inside its row (ld and the
-        // row bases are multiples of 8); octets past the chunk read the
-        // row's first one: they only feed outputs past nout
-        raw[S][k] = *reinterpret_cast<const uint2*>(xrow + (uint32_t)((m < nocts && off < L) ? off : 0));
+        // row bases are multiples of 8); octets past the chunk or past the
+        // row's span read the row's first one: they feed no output that is
+        // stored
+        raw[S][k] = *reinterpret_cast<const uint2*>(xrow + (uint32_t)((m <= nw && off < L) ? off : 0));
       }
       const int dd = tid % kU8BD, cb = min(tid / kU8BD, kU8BC - 1);
       const int d = min(d0 + dd, dlast);
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
           w[2] = next_lane(w[0], more ? rotate_lane(nx.x) : 0u);
           w[3] = next_lane(w[1], more ? rotate_lane(nx.y) : 0u);
           const int m = lane + 64 * k;
-          if (m < nocts) {
+          if (m < nwr[S]) {
             char* p = row + 16 * m;                // position 8m of copy 0 (2 bytes a sample)
             u32x8 e, e2, o, o2;
             copies16<0>(w, e, e2);
