@@ -360,6 +360,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // ring position of chunk sample 0
   const int32_t pv = (RING && A.R > 0) ? (int32_t)((p0 + vring) % A.R) : 0;
   const int32_t* __restrict__ dl = A.delays + (int64_t)d0 * C;   // DM d0's delays
+  const int32_t* __restrict__ dz = A.delays + (int64_t)dlast * C; // the block's last DM's
   // LDS: one stage (or two, double-buffered) of BC rows x NCP copies x RS
   // samples followed by the stage's [BC][BD] window offsets
   constexpr bool DB = (P & 2) != 0;
@@ -383,6 +384,16 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   Staged<TIN, RING> st[NSET][RPW][KM];
   RowMeta rm[NSET][RPW];
   int basen[RPW];        // s[d0][c] of the row in the block after next (vector load, lands early)
+  int lastn[RPW];        // s[dlast][c] of the same row
+  // With four copies and one wave per row, a row stages only the span its
+  // block's windows read: they start at most (s[dlast][c] - s[d0][c] + 3)
+  // & ~3 positions in (delays grow with DM), so the consumers read the first
+  // that / 4 + BT / 4 quads of each copy, and the copies of the last of them
+  // take samples from the quad after it.  A row near the top of the band,
+  // where the delay spread is small, stages that much less.  (Not in the
+  // persistent kernel, whose registers are full.)
+  constexpr bool TRIM = NCP == 4 && WPR == 1 && SKIP_IDLE;
+  int rowq[NSET][RPW];   // quads staged of the row (live: m < rowq)
   float fitn[NSET][RPW]; // bandpass value of the row being staged (loaded with its quads)
   int32_t rowt[NSET][RPW]; // chunk index of the staged row's window start (uniform)
   int offreg[NSET] = {};
@@ -416,11 +427,13 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     constexpr int S = decltype(set_c)::value;
     // the window bases of the rows of the block after this one go first:
     // the next call waits for them, and so for nothing issued after them
-    int base_now[RPW];
+    int base_now[RPW], last_now[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       base_now[rr] = __builtin_amdgcn_readfirstlane(basen[rr]);
+      if (TRIM) last_now[rr] = __builtin_amdgcn_readfirstlane(lastn[rr]);
       basen[rr] = dl[min(cb0 + BC + row_of(rr), C - 1) + lane * A.zero];
+      if (TRIM) lastn[rr] = dz[min(cb0 + BC + row_of(rr), C - 1) + lane * A.zero];
     }
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
@@ -430,6 +443,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         const int64_t a = t0 + (base & ~3);
         const int32_t aw = (int32_t)(a - vring);     // chunk index of the window start
         rowt[S][rr] = aw;
+        const int rq = TRIM ? min(mend, ((last_now[rr] - (base & ~3)) >> 2) + BT / 4 + 1) : mend;
+        rowq[S][rr] = rq;
         const TIN* xrow = static_cast<const TIN*>(A.x) + (int64_t)c * A.ld;
         const float* ringrow = RING ? A.ring + (int64_t)c * A.R : nullptr;
         load_meta(rm[S][rr], c, a);
@@ -437,7 +452,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           const int m = m0 + lane + 64 * k;
-          issue<TIN, CLEAN, RING>(st[S][rr][k], A, xrow, ringrow, aw + 4 * m, m < mend, pv);
+          issue<TIN, CLEAN, RING>(st[S][rr][k], A, xrow, ringrow, aw + 4 * m, m < rq, pv);
         }
       }
     }
@@ -474,7 +489,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
         // Fast path (uniform per row): the wave's quads all lie inside the
         // chunk and none of their chunks or spectra is flagged, so a quad
         // needs only widening and the bandpass subtraction.
-        const int32_t t_lo = rowt[S][rr] + 4 * m0, t_hi = rowt[S][rr] + 4 * mend;
+        const int rq = rowq[S][rr];
+        const int32_t t_lo = rowt[S][rr] + 4 * m0, t_hi = rowt[S][rr] + 4 * rq;
         bool fast = t_lo >= 0 && t_hi <= (int32_t)A.L;
         if (CLEAN) {
           uint32_t gor = 0;
@@ -490,7 +506,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
               const int m = m0 + lane + 64 * k;
-              if (m < mend) *reinterpret_cast<float4*>(row + 4 * m) = lo[k];
+              if (m < rq) *reinterpret_cast<float4*>(row + 4 * m) = lo[k];
             }
           } else {
 #pragma unroll
@@ -506,7 +522,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
               hi.y = next_quad(lo[k].y, more ? wave_rotate(nx.y) : 0.0f);
               hi.z = next_quad(lo[k].z, more ? wave_rotate(nx.z) : 0.0f);
               const int m = m0 + lane + 64 * k;
-              if (m < mend) {
+              if (m < rq) {
                 const float4 l = lo[k];
                 // copy r holds the window shifted by r samples
                 float* p = row + 4 * m;
@@ -536,7 +552,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
             const int m = m0 + lane + 64 * k;
-            lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit, rowt[S][rr] + 4 * m, m < mend);
+            lo[k] = finish<TIN, CLEAN, RING>(st[S][rr][k], A, rm[S][rr], fit, rowt[S][rr] + 4 * m, m < rq);
           }
           write_quads(lo);
         }
@@ -562,6 +578,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   for (int rr = 0; rr < RPW; ++rr) {
     const int c = row_of(rr);
     basen[rr] = dl[min(c, C - 1)];
+    if (TRIM) lastn[rr] = dz[min(c, C - 1)];
   }
   // Single buffer: per block, issue the loads of block k+1, accumulate block
   // k, barrier, write block k+1, barrier.  Double buffer: block k+1 is
