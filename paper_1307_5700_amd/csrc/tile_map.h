@@ -16,7 +16,7 @@ struct TileIdx {
 // cheaper), each XCD takes its share of the full blocks' tiles first and its
 // share of the partial block's last, so the cheap tiles fill the final,
 // partly occupied round.  A bijection from [0, nd*nt) onto the tiles.
-__device__ inline TileIdx xcd_tile(int bid, int nd, int nt, bool partial) {
+__host__ __device__ inline TileIdx xcd_tile(int bid, int nd, int nt, bool partial) {
   const int ntile = nd * nt;
   const int xcd = bid & 7, slot = bid >> 3;
   const int q8 = ntile >> 3, rem = ntile & 7;
