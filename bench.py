@@ -23,7 +23,7 @@ measure the systems patterns on their own inputs:
 
   batch      eight uint8 beams with uneven plans (512-2048 channels, 320-1280
              DMs, chunks of 16384-131072 samples) as one HIP graph per chunk
-             step around one batched launch, tiling from the autotuner;
+             step around one persistent launch, tiling from the autotuner;
              beside it the same beams in FP32 one by one, eagerly (the plain
              single-beam path), and the speedup between the two
   serve      32 uint8 beams of 1024 channels / 640 DMs fed as Poisson chunk
@@ -646,7 +646,7 @@ def bench_paper_u8(args):
 
 def bench_batch(args):
     """Eight uneven uint8 beams: one captured chunk step (RFI passes, one
-    dedispersion launch, detection) against the same beams in
+    persistent dedispersion launch, detection) against the same beams in
     FP32 one at a time."""
     import torch
     from paper_1307_5700_amd import api as A

@@ -420,16 +420,14 @@ typedef struct {
   mb_norm* d_norm;             /* nullable */
 } mb_batch_item;
 
-/* Bytes of caller-owned device workspace for a batch of nitems (256 per
- * launch of up to 16 items; reserved: the current launch reads and writes
- * none of it). */
+/* Bytes of caller-owned device workspace for a batch of nitems (a tile
+ * counter per launch of up to 16 items). */
 mb_status dedisp_batch_workspace_size(int32_t nitems, size_t* bytes);
 
 /* Dedisperses many beams' chunks (Sec. 2, multibeam: beams are independent)
- * in one launch per 16 items: one workgroup per (item, DM block, time tile),
- * items in order of decreasing channel count, so that the heaviest tiles
- * start first and beams with uneven channel counts, DM plans and chunk
- * lengths share the GPU.
+ * in one persistent launch per 16 items: workgroups take (item, DM block,
+ * time tile) work from an atomic counter, heaviest channel counts first, so
+ * beams with uneven channel counts, DM plans and chunk lengths share the GPU.
  * Every item gives exactly the result dedisp_execute gives it alone (same
  * summation order), including streaming beams.  All plans must share the
  * storage type and the tiling (plan_info dm_block/time_tile/chan_block, set

@@ -448,7 +448,7 @@ def alloc_batch_work(nitems: int, device=None) -> torch.Tensor:
 
 
 def execute_batch(jobs, work: torch.Tensor | None = None, stream=None):
-    """One dedispersion launch (per 16 jobs) over many beams.
+    """One persistent dedispersion launch (per 16 jobs) over many beams.
 
     jobs: list of dicts with keys plan, x, and optionally rfi_state, out,
     norm (tensor, True to allocate, False for none) and beam.  Returns a list
@@ -613,7 +613,7 @@ class ChunkGraph:
 class BatchGraph:
     """The chunk step of several beams captured as one HIP graph.
 
-    Per beam the RFI pass, then one batched dedispersion launch
+    Per beam the RFI pass, then one batched persistent dedispersion launch
     over every beam (with normalisation), then per beam detection, captured
     by the library (dedisp_step_graph_create).  All plans must share the
     storage type and the tiling.  Capture once every beam is in steady state

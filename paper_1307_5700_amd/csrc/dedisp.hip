@@ -305,7 +305,7 @@ __device__ inline void add_shifted<2>(float4 (&acc)[2], const float4 (&v)[2], in
 
 // One (DM block, time tile) of one launch item; all threads of the
 // workgroup call it.  lds: the dynamic LDS of the workgroup.
-template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
+template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P, bool SKIP_IDLE>
 __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* relb,
                                             const float* fit32, float* lds,
                                             int dblock, int ttile) {
@@ -390,8 +390,9 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // & ~3 positions in (delays grow with DM), so the consumers read the first
   // that / 4 + BT / 4 quads of each copy, and the copies of the last of them
   // take samples from the quad after it.  A row near the top of the band,
-  // where the delay spread is small, stages that much less.
-  constexpr bool TRIM = NCP == 4 && WPR == 1;
+  // where the delay spread is small, stages that much less.  (Not in the
+  // persistent kernel, whose registers are full.)
+  constexpr bool TRIM = NCP == 4 && WPR == 1 && SKIP_IDLE;
   int rowq[NSET][RPW];   // quads staged of the row (live: m < rowq)
   float fitn[NSET][RPW]; // bandpass value of the row being staged (loaded with its quads)
   int32_t rowt[NSET][RPW]; // chunk index of the staged row's window start (uniform)
@@ -788,8 +789,8 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
     zero_sums();
     // a consumer whose DMs all lie past the grid's last (the last DM block
     // of a grid that BD does not divide) reads nothing, but keeps the
-    // barriers
-    const bool idle = d0 + aw * G > dlast;
+    // barriers (not in the persistent kernel, whose registers are full)
+    const bool idle = SKIP_IDLE && d0 + aw * G > dlast;
     int cur = 0;
     for (int cb0 = 0; cb0 < C; cb0 += BC) {
       if (!idle) accumulate(cb0, cur);
@@ -858,31 +859,34 @@ __global__ __launch_bounds__(64 * NW) void dedisp_kernel(DedispArgs A, const int
   const TileIdx ti = xcd_tile(blockIdx.x, A.n_dblocks, A.n_ttiles, A.ndms % BD != 0);
   const int dblock = ti.dblock, ttile = ti.ttile;
   if (dblock >= A.n_dblocks || ttile >= A.n_ttiles) return;   // uniform: never taken
-  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P>(A, relb, fit32, reinterpret_cast<float*>(lds4),
+  dedisp_tile<TIN, CLEAN, RING, NW, G, Q, BC, P, true>(A, relb, fit32, reinterpret_cast<float*>(lds4),
                                                        dblock, ttile);
 }
 
-// One launch over the tiles of several items (beams, chunks, plans of one
-// tiling).  Item i owns workgroups [tile0, tile0 + its tiles), items in
-// order of decreasing channel count (the hardware hands out workgroups in
-// order, so the heaviest tiles start first); each item's range starts at a
-// multiple of 8, so its tiles map to the XCDs as a single launch's do, and
-// the padding workgroups exit at once.
+// Persistent launch over the tiles of several items (beams, chunks, plans of
+// one tiling).  Workgroups take tiles from an atomic counter in item order,
+// heaviest items first, until the counter passes the total; every
+// workgroup reaches that exit.
 template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC, int P>
 __global__ __launch_bounds__(64 * NW) void dedisp_batch_kernel(BatchArgs B) {
   extern __shared__ float4 lds4[];
-  constexpr int BD = ((P & 8) ? NW - ((P & 64) ? 8 : 4) : NW) * G;
-  const int t = blockIdx.x;
-  int i = 0;
-  while (i + 1 < B.nitems && t >= B.item[i + 1].tile0) ++i;
-  const BatchItem& it = B.item[i];
-  const int local = t - it.tile0;
-  if (local >= it.a.n_dblocks * it.a.n_ttiles) return;   // padding (uniform)
-  const TileIdx ti = xcd_tile(local, it.a.n_dblocks, it.a.n_ttiles, it.a.ndms % BD != 0);
-  dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC, P>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
-                                                      ti.dblock, ti.ttile);
+  __shared__ int tile_sh;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) tile_sh = atomicAdd(B.counter, 1);
+    __syncthreads();
+    const int t = tile_sh;
+    if (t >= B.total) break;
+    int i = 0;
+    while (i + 1 < B.nitems && t >= B.item[i + 1].tile0) ++i;
+    const BatchItem& it = B.item[i];
+    const int local = t - it.tile0;
+    dedisp_tile<TIN, CLEAN, true, NW, G, Q, BC, P, false>(it.a, it.relb, it.fit32, reinterpret_cast<float*>(lds4),
+                                                local % it.a.n_dblocks, local / it.a.n_dblocks);
+  }
 }
 
+__global__ void zero_int_kernel(int* p) { *p = 0; }
 
 // Device-side stream position of a beam: st[0] samples seen since the stream
 // (re)started, st[1] absolute index of the last chunk's first output, st[2]
@@ -939,13 +943,24 @@ __global__ __launch_bounds__(256) void ring_update_kernel(const TIN* __restrict_
   ring[(int64_t)c * R + (seen + t) % R] = v;
 }
 
+// The P a kernel variant is compiled with: the second prefetch set (P bit 4)
+// does not fit the registers of the persistent kernel (its tile loop holds
+// more state), which keeps one block in flight.  The LDS layout and every
+// addition are the same.
+template <typename TIN>
+constexpr int kernel_p(int P, bool ring, bool batch) {
+  (void)ring;
+  return ((P & 16) != 0 && batch) ? (P & ~16) : P;
+}
+
 template <typename TIN, bool CLEAN, bool RING, int NW, int G, int Q, int BC, int P>
 hipError_t launch_one(const DedispArgs& a, const int32_t* relb, const float* fit32, size_t lds,
                       hipStream_t s) {
   // the LDS limit was raised when the plan was created (dedisp_prepare), so
   // a launch makes no attribute call and is safe inside stream capture
   const unsigned grid = (unsigned)a.n_dblocks * (unsigned)a.n_ttiles;
-  hipLaunchKernelGGL((dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC, P>), dim3(grid), dim3(64 * NW), lds, s,
+  constexpr int KP = kernel_p<TIN>(P, RING, false);
+  hipLaunchKernelGGL((dedisp_kernel<TIN, CLEAN, RING, NW, G, Q, BC, KP>), dim3(grid), dim3(64 * NW), lds, s,
                      a, relb, fit32);
   return hipGetLastError();
 }
@@ -1041,23 +1056,28 @@ hipError_t launch_beam_seek(int64_t* seen_dev, int64_t base, hipStream_t s) {
 
 namespace {
 template <typename TIN, bool CLEAN, int NW, int G, int Q, int BC, int P>
-hipError_t launch_batch_one(BatchArgs& b, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC, P>), dim3((unsigned)b.total), dim3(64 * NW), lds,
-                     s, b);
+hipError_t launch_batch_one(BatchArgs& b, size_t lds, int grid_cap, hipStream_t s) {
+  const int grid = b.total < grid_cap ? b.total : grid_cap;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, b.counter);
+  hipLaunchKernelGGL((dedisp_batch_kernel<TIN, CLEAN, NW, G, Q, BC, kernel_p<TIN>(P, true, true)>), dim3(grid),
+                     dim3(64 * NW), lds, s, b);
   return hipGetLastError();
 }
 
-// Raises the LDS limit of every kernel variant of one (storage type, tiling).
+// Raises the LDS limit of every kernel variant of one (storage type, tiling)
+// and returns the persistent kernel's resident workgroups per CU at `lds`
+// bytes, without and with cleaning.
 template <typename TIN, int NW, int G, int Q, int BC, int P>
-hipError_t prepare_one(size_t lds) {
-  (void)lds;
+hipError_t prepare_one(size_t lds, int occ[2]) {
+  constexpr int P0 = kernel_p<TIN>(P, false, false), PR = kernel_p<TIN>(P, true, false),
+                PB = kernel_p<TIN>(P, true, true);
   const void* ks[6] = {
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, true, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, true, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, false, NW, G, Q, BC, P>),
-      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, true, NW, G, Q, BC, P>)};
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, false, NW, G, Q, BC, P0>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, false, true, NW, G, Q, BC, PR>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, false, NW, G, Q, BC, P0>),
+      reinterpret_cast<const void*>(dedisp_kernel<TIN, true, true, NW, G, Q, BC, PR>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, false, NW, G, Q, BC, PB>),
+      reinterpret_cast<const void*>(dedisp_batch_kernel<TIN, true, NW, G, Q, BC, PB>)};
   hipError_t e;
   for (const void* k : ks) {
     // dynamic + static LDS of a workgroup must fit the CU's 160 KiB
@@ -1067,43 +1087,47 @@ hipError_t prepare_one(size_t lds) {
     if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_max)) != hipSuccess)
       return e;
   }
+  for (int c = 0; c < 2; ++c)
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[c], ks[4 + c], 64 * NW, lds)) != hipSuccess)
+      return e;
   return hipSuccess;
 }
 
 template <typename TIN>
-hipError_t prepare_tiled(const Tiling& t, size_t lds) {
+hipError_t prepare_tiled(const Tiling& t, size_t lds, int occ[2]) {
 #define MBTP_TILE(NW_, G_, Q_, BC_, P_) \
   if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_ && t.P == P_) \
-    return prepare_one<TIN, NW_, G_, Q_, BC_, P_>(lds);
+    return prepare_one<TIN, NW_, G_, Q_, BC_, P_>(lds, occ);
   MBTP_TILINGS(MBTP_TILE)
 #undef MBTP_TILE
   return hipErrorInvalidValue;
 }
 
 template <typename TIN, bool CLEAN>
-hipError_t launch_batch_tiled(const Tiling& t, BatchArgs& b, size_t lds, hipStream_t s) {
+hipError_t launch_batch_tiled(const Tiling& t, BatchArgs& b, size_t lds, int grid_cap, hipStream_t s) {
 #define MBTP_TILE(NW_, G_, Q_, BC_, P_) \
   if (t.NW == NW_ && t.G == G_ && t.Q == Q_ && t.BC == BC_ && t.P == P_) \
-    return launch_batch_one<TIN, CLEAN, NW_, G_, Q_, BC_, P_>(b, lds, s);
+    return launch_batch_one<TIN, CLEAN, NW_, G_, Q_, BC_, P_>(b, lds, grid_cap, s);
   MBTP_TILINGS(MBTP_TILE)
 #undef MBTP_TILE
   return hipErrorInvalidValue;
 }
 }  // namespace
 
-hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds, hipStream_t s) {
+hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds,
+                               int grid_cap, hipStream_t s) {
   switch (dtype) {
-    case 0: return clean ? launch_batch_tiled<uint8_t, true>(t, b, lds, s) : launch_batch_tiled<uint8_t, false>(t, b, lds, s);
-    case 1: return clean ? launch_batch_tiled<__half, true>(t, b, lds, s) : launch_batch_tiled<__half, false>(t, b, lds, s);
-    default: return clean ? launch_batch_tiled<float, true>(t, b, lds, s) : launch_batch_tiled<float, false>(t, b, lds, s);
+    case 0: return clean ? launch_batch_tiled<uint8_t, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<uint8_t, false>(t, b, lds, grid_cap, s);
+    case 1: return clean ? launch_batch_tiled<__half, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<__half, false>(t, b, lds, grid_cap, s);
+    default: return clean ? launch_batch_tiled<float, true>(t, b, lds, grid_cap, s) : launch_batch_tiled<float, false>(t, b, lds, grid_cap, s);
   }
 }
 
-hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds) {
+hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]) {
   switch (dtype) {
-    case 0: return prepare_tiled<uint8_t>(t, lds);
-    case 1: return prepare_tiled<__half>(t, lds);
-    default: return prepare_tiled<float>(t, lds);
+    case 0: return prepare_tiled<uint8_t>(t, lds, occ);
+    case 1: return prepare_tiled<__half>(t, lds, occ);
+    default: return prepare_tiled<float>(t, lds, occ);
   }
 }
 

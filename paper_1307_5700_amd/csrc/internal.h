@@ -128,19 +128,20 @@ struct DedispArgs {
   const int64_t* seen_dev;   // beam's device-side sample count (ring position), or null
 };
 
-// One item of a batched launch, and the launch's arguments
+// One item of a batched persistent launch, and the launch's arguments
 // (passed by value: at most kMaxBatch items, within the 4 KiB argument limit).
 constexpr int kMaxBatch = 16;
 struct BatchItem {
   DedispArgs a;
   const int32_t* relb;
   const float* fit32;
-  int32_t tile0;             // first workgroup of this item (a multiple of 8)
+  int32_t tile0;             // first global tile of this item
   int32_t pad;
 };
 struct BatchArgs {
   BatchItem item[kMaxBatch];
   int32_t nitems, total;
+  int* counter;              // zeroed by the launcher before the launch
 };
 static_assert(sizeof(BatchArgs) <= 4096, "batch arguments exceed the kernel argument limit");
 
@@ -174,14 +175,15 @@ hipError_t launch_dedisp(int dtype, bool clean, bool ring, const Tiling& t, cons
                          const int32_t* relb, const float* fit32, size_t lds_bytes,
                          hipStream_t s);
 
-// One launch over the tiles of all items (same dtype, cleaning
-// and tiling); lds = the largest item's LDS; b.total workgroups, item
-// ranges starting at multiples of 8.
-hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds, hipStream_t s);
+// One persistent launch over the tiles of all items (same dtype, cleaning
+// and tiling); lds = the largest item's LDS; at most grid_cap workgroups.
+hipError_t launch_dedisp_batch(int dtype, bool clean, const Tiling& t, BatchArgs& b, size_t lds,
+                               int grid_cap, hipStream_t s);
 
 // At plan creation: raises the LDS limit of every dedispersion kernel of the
-// storage type and tiling.
-hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds);
+// storage type and tiling, and returns the persistent kernel's resident
+// workgroups per CU at `lds` bytes (occ[0] without, occ[1] with cleaning).
+hipError_t dedisp_prepare(int dtype, const Tiling& t, size_t lds, int occ[2]);
 
 // Integer kernel for 8-bit data without cleaning (dedisp_u8.hip): 12
 // consumer waves of kU8G DMs, kU8BT outputs per tile, kU8BC channels per

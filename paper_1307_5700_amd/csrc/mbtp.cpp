@@ -96,6 +96,7 @@ struct mb_plan {
   int n_dblocks = 0;
   int relb_ld = 0;
   int cus = 0;                 // compute units of the plan's device
+  int batch_occ[2] = {1, 1};   // persistent workgroups per CU (no cleaning, cleaning)
   // 8-bit plans: the exact integer kernel for chunks without cleaning, when
   // its staging fits (copy length rs8 samples, lds8 bytes, offsets d_relb8)
   bool u8_int = false;
@@ -137,7 +138,7 @@ int32_t span_max(const mb_plan& p, int BD) {
 constexpr int64_t kMaxSamps = int64_t(1) << 30;
 constexpr int32_t kMaxDms = 65535;                 // DM trials of one plan
 constexpr int32_t kMaxClassifyDms = 4000;          // per-row tables of one cluster in 64 KB of LDS
-constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, with 256 bytes to spare
+constexpr size_t kMaxLds = 160 * 1024 - 256;   // gfx950 LDS per workgroup, less the persistent kernel's static LDS
 
 // LDS copy length: the largest window start (span + 3, rounded down to 4)
 // plus the tile, plus the quad read after the last one.
@@ -316,7 +317,7 @@ mb_status dedisp_plan_create(const mb_plan_desc* desc, mb_plan** out) {
     return fail(MB_ENOMEM, "hipMalloc of %zu bytes failed", tb + rb);
   }
   e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
-  if (e == hipSuccess) e = dedisp_prepare(d.in_dtype, p->tiling, p->lds);
+  if (e == hipSuccess) e = dedisp_prepare(d.in_dtype, p->tiling, p->lds, p->batch_occ);
   if (e == hipSuccess) e = hipMemcpy(p->d_delays, p->h_delays.data(), tb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_relb(p->d_delays, d.nchans, d.ndms, p->tiling.BD(), p->rs, p->tiling.copies(),
                                         p->relb_ld, p->d_relb, nullptr);
@@ -701,8 +702,10 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
   for (int32_t l = 0; l < nlaunch; ++l) {
     BatchArgs b;
     memset(&b, 0, sizeof(b));
+    b.counter = reinterpret_cast<int*>(static_cast<char*>(d_work) + 256 * (size_t)l);
     size_t lds = 0;
     int32_t total = 0;
+    int grid_cap = 1 << 30;
     for (int32_t k = l * kMaxBatch; k < nitems && k < (l + 1) * kMaxBatch; ++k) {
       const Prepared& q = P[order[k]];
       if (q.nout <= 0) continue;
@@ -711,11 +714,14 @@ mb_status dedisp_execute_batch(const mb_batch_item* items, int32_t nitems, void*
       bi.relb = q.plan->d_relb;
       bi.fit32 = q.fit32;
       bi.tile0 = total;
-      total += (q.a.n_dblocks * q.a.n_ttiles + 7) & ~7;   // XCD-aligned item ranges
+      total += q.a.n_dblocks * q.a.n_ttiles;
       if (q.plan->lds > lds) lds = q.plan->lds;
+      const int occ = q.plan->batch_occ[clean0 ? 1 : 0];
+      const int cap = q.plan->cus * (occ < 1 ? 1 : occ);
+      if (cap < grid_cap) grid_cap = cap;
     }
     b.total = total;
-    if (total > 0) HIP_TRY(launch_dedisp_batch(p0->desc.in_dtype, clean0, p0->tiling, b, lds, s));
+    if (total > 0) HIP_TRY(launch_dedisp_batch(p0->desc.in_dtype, clean0, p0->tiling, b, lds, grid_cap, s));
   }
   for (int32_t i = 0; i < nitems; ++i) {
     mb_status st = finish_item(P[i], s);

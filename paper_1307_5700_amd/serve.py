@@ -6,7 +6,7 @@ iteration).  The server keeps every admitted beam's overlap ring resident on
 the device, admits beams by their HBM footprint (the memory trade-off of
 Sec. 3: input, output and shift buffer per beam must fit the GPU), and runs
 ready chunks as soon as a slot frees up: chunks that are ready together go
-out as one batched launch, several launches overlap on separate
+out as one batched persistent launch, several launches overlap on separate
 streams.  A beam has at most one chunk on the device at a time (its ring is
 sequential).  Each chunk's latency runs from its arrival to the moment its
 candidates are on the host.

@@ -1,4 +1,4 @@
-"""Batched launch: every item equals its own single launch, bit for
+"""Batched persistent launch: every item equals its own single launch, bit for
 bit, for beams with uneven channel counts, DM plans and chunk lengths."""
 import numpy as np
 import pytest

@@ -120,7 +120,7 @@ def test_autotuner_picks_and_caches(tmp_path):
 
 
 def test_batch_graph_replays_match_eager_batches():
-    """Three uneven beams in one captured step (RFI passes, one batched
+    """Three uneven beams in one captured step (RFI passes, one persistent
     launch, detection); every replay equals an eager batched step of a
     parallel set of beams fed the same chunks."""
     A = api()
