@@ -40,9 +40,10 @@ def _run(plan, x, ld, integer=None):
 # (channels, DMs, samples): 16-bit partials widened at 256 channels (C above
 # 256, not a multiple of 256 or of 4), a partial last DM block (DMs not a
 # multiple of 48), ragged last time tiles, a single partial tile, a single
-# channel and a single DM.
+# channel and a single DM, and a chunk whose last octet straddles its end
+# (rows padded to a multiple of 8).
 SHAPES = [(256, 64, 8192), (300, 100, 12000), (1024, 97, 16384), (517, 48, 9000), (1, 1, 600),
-          (64, 49, 1200), (2048, 130, 20000)]
+          (64, 49, 1200), (2048, 130, 20000), (333, 51, 8195)]
 
 
 @pytest.mark.parametrize("C,nd,T", SHAPES, ids=[f"{c}ch_{d}dm_{t}" for c, d, t in SHAPES])
@@ -116,3 +117,33 @@ def test_cleaning_and_other_storage_types_take_the_float_kernels():
     xc = synth.render(bc, sc)
     D, nout = _run(pc, xc, 30000, integer=False)
     assert np.array_equal(D, oracle.dedisperse(xc, sc).astype(np.float32))
+
+
+def test_captured_step_on_the_integer_kernel_replays_exactly():
+    """A single-shot 8-bit step without cleaning, captured as a HIP graph
+    (integer dedispersion, normalisation, detection), replays to the eager
+    step's outputs and candidates with new data in the input buffer."""
+    A = api()
+    T = 8192
+    b, s = _beam(512, 96, T * 4)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    xbuf = torch.zeros((512, T), dtype=torch.uint8, device="cuda")
+    xbuf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, :T])))
+    g = A.ChunkGraph(plan, xbuf, rfi=False, nsigma=6.0)
+    for k in range(4):
+        chunk = torch.from_numpy(np.ascontiguousarray(x[:, k * T:(k + 1) * T])).cuda()
+        xbuf.copy_(chunk)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        out, norm, nout, _ = plan.execute(chunk)
+        assert plan.last_integer_kernel
+        det = plan.detect(out, nout, norm, 6.0)
+        torch.cuda.synchronize()
+        assert torch.equal(g.out[:, :nout], out[:, :nout]), k
+        ref = oracle.dedisperse(x[:, k * T:(k + 1) * T], s)
+        assert np.array_equal(g.out[:, :nout].cpu().numpy(), ref.astype(np.float32)), k
+        gc, gn = plan.candidates_to_host(g.det[0], g.det[1])
+        ec, en = plan.candidates_to_host(det[0], det[1])
+        assert gn == en and np.array_equal(gc, ec), k
