@@ -41,7 +41,7 @@ constexpr int kWaves = kProd + kCons;
 constexpr int kFold = 256;                       // channels per 16-bit partial
 constexpr int kPF = 4;                           // blocks of producer loads in flight
 static_assert(kProd == kU8BC && kCons == 12 && kU8BT == 64 * 8, "integer tile");
-static_assert(kFold % kU8BC == 0, "partials close on block boundaries");
+static_assert(kFold % kU8BC == 0 && kU8BC == 4, "partials close on block boundaries; four channels a block");
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -276,44 +276,64 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
   // a consumer whose DMs all lie past the grid's last reads nothing, but
   // keeps the barriers
   const bool idle = d0 + aw * kU8G > dlast;
+  // The adds of a block's last channel wait until after the barrier that
+  // ends the block (its reads have landed by then: the barrier waits for
+  // them), where they overlap the next block's offset reads.
+  uint4 vp[kU8G];                                  // last channel of the previous block
+  bool pend = false;
+  int pcb0 = 0;
+  auto add4 = [&](const uint4 (&t)[kU8G]) {
+#pragma unroll
+    for (int g = 0; g < kU8G; ++g) {
+      acc[g][0] = add_u16x2(acc[g][0], t[g].x);
+      acc[g][1] = add_u16x2(acc[g][1], t[g].y);
+      acc[g][2] = add_u16x2(acc[g][2], t[g].z);
+      acc[g][3] = add_u16x2(acc[g][3], t[g].w);
+    }
+  };
+  auto settle = [&] {                              // the deferred adds, then the block's fold
+    if (pend) {
+      add4(vp);
+      if (((pcb0 + kU8BC) & (kFold - 1)) == 0) fold();
+      pend = false;
+    }
+  };
   int cur = 0;
   for (int cb0 = 0; cb0 < C; cb0 += kU8BC) {
     if (!idle) {
       const char* const st = lds + cur * stage_bytes;
       const int* const offs = reinterpret_cast<const int*>(st + kU8BC * row_bytes) + aw * kU8G;
       const char* const lb = st + 16 * lane;
-      // the block's offsets first; then the reads of channels 0 and 1, and
-      // per channel cb the adds of each DM followed at once by the read of
-      // channel cb+2 into the registers they freed (two register sets, up to
-      // 2G reads in flight)
+      // the block's offsets, the previous block's deferred adds while they
+      // are read, then the reads of channels 0 and 1, and per channel the
+      // adds followed at once by the read of the channel two on into the
+      // registers they freed; the last channel's adds are deferred
       int o[kU8BC][4];
 #pragma unroll
       for (int cb = 0; cb < kU8BC; ++cb) {
         const int4 o4 = *reinterpret_cast<const int4*>(offs + cb * kU8BD);
         o[cb][0] = o4.x; o[cb][1] = o4.y; o[cb][2] = o4.z; o[cb][3] = o4.w;
       }
+      settle();
       uint4 v[2][kU8G];
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int g = 0; g < kU8G; ++g) v[0][g] = *reinterpret_cast<const uint4*>(lb + o[0][g]);
 #pragma unroll
-        for (int g = 0; g < kU8G; ++g) v[cb][g] = *reinterpret_cast<const uint4*>(lb + o[cb][g]);
+      for (int g = 0; g < kU8G; ++g) v[1][g] = *reinterpret_cast<const uint4*>(lb + o[1][g]);
+      add4(v[0]);
 #pragma unroll
-      for (int cb = 0; cb < kU8BC; ++cb) {
+      for (int g = 0; g < kU8G; ++g) v[0][g] = *reinterpret_cast<const uint4*>(lb + o[2][g]);
+      add4(v[1]);
 #pragma unroll
-        for (int g = 0; g < kU8G; ++g) {
-          const uint4 t = v[cb & 1][g];
-          acc[g][0] = add_u16x2(acc[g][0], t.x);
-          acc[g][1] = add_u16x2(acc[g][1], t.y);
-          acc[g][2] = add_u16x2(acc[g][2], t.z);
-          acc[g][3] = add_u16x2(acc[g][3], t.w);
-          if (cb + 2 < kU8BC) v[cb & 1][g] = *reinterpret_cast<const uint4*>(lb + o[cb + 2][g]);
-        }
-      }
-      if (((cb0 + kU8BC) & (kFold - 1)) == 0) fold();
+      for (int g = 0; g < kU8G; ++g) vp[g] = *reinterpret_cast<const uint4*>(lb + o[3][g]);
+      add4(v[0]);
+      pend = true;
+      pcb0 = cb0;
     }
     __syncthreads();
     cur ^= 1;
   }
+  settle();
   // the producers' steps past the last block (their loop runs in groups of kPF)
   const int nblk = (C + kU8BC - 1) / kU8BC;
   for (int k = nblk; k % kPF != 0; ++k) __syncthreads();
