@@ -147,3 +147,21 @@ def test_captured_step_on_the_integer_kernel_replays_exactly():
         gc, gn = plan.candidates_to_host(g.det[0], g.det[1])
         ec, en = plan.candidates_to_host(det[0], det[1])
         assert gn == en and np.array_equal(gc, ec), k
+
+
+def test_paper_beam_in_8_bits_at_full_size():
+    """The 1024-channel, 65536-sample, 640-DM beam stored in 8 bits (the
+    paper_u8 workload): the integer kernel runs, sampled rows equal the
+    oracle's sums exactly, and the whole plane equals the float kernel's."""
+    A = api()
+    b = synth.paper_beam(dtype="u8")
+    plan = A.Plan.from_beam(b)
+    s = plan.delays()
+    x = synth.render(b, s)
+    D8, nout = _run(plan, x, x.shape[1], integer=True)
+    assert nout == x.shape[1] - int(s.max())
+    rows = np.array(sorted({0, 1, 47, 48, 320, 639} | {p.dm_index for p in b.pulses}))
+    ref = oracle.dedisperse_rows(x, s, rows, nout)
+    assert np.array_equal(D8[rows].astype(np.float64), ref)
+    Df, _ = _run(plan, x, x.shape[1] + 4, integer=False)
+    assert np.array_equal(Df, D8)
