@@ -3,11 +3,13 @@
 //
 //   D[d][t] = sum_c x[c][t + s[d][c]],   x[c][t] in 0..255
 //
-// The tile and schedule are those of the warp-specialised float kernel: a
-// workgroup of 16 wave64s covers 48 adjacent DMs x 512 consecutive outputs.
-// Four producer waves stage a block of 4 channels into LDS while twelve
-// consumer waves (4 DMs each) accumulate the block before it, over two LDS
-// stages with one barrier per block.
+// The tile is that of the warp-specialised float kernel: a workgroup of 16
+// wave64s covers 48 adjacent DMs x 512 consecutive outputs.  Four producer
+// waves stage a block of 4 channels into LDS while twelve consumer waves
+// (4 DMs each) accumulate the block before it, over two LDS stages with one
+// barrier per block.  Producers keep four blocks of loads in flight and
+// stage each row only as far as its block's windows read; consumers add a
+// block's last channel after the barrier that ends it.
 //
 // What changes is the width of a term.  Samples are staged as 16-bit
 // integers, in eight copies shifted by 0..7 samples, so every (DM, channel)
