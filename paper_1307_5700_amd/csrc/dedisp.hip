@@ -390,9 +390,10 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, const int32_t* 
   // & ~3 positions in (delays grow with DM), so the consumers read the first
   // that / 4 + BT / 4 quads of each copy, and the copies of the last of them
   // take samples from the quad after it.  A row near the top of the band,
-  // where the delay spread is small, stages that much less.  (Not in the
-  // persistent kernel, whose registers are full.)
-  constexpr bool TRIM = NCP == 4 && WPR == 1 && SKIP_IDLE;
+  // where the delay spread is small, stages that much less.  The persistent
+  // kernel, whose tile loop leaves few registers, trims only cleaned 8-bit
+  // rows (its other variants would spill).
+  constexpr bool TRIM = NCP == 4 && WPR == 1 && (SKIP_IDLE || (sizeof(TIN) == 1 && CLEAN));
   int rowq[NSET][RPW];   // quads staged of the row (live: m < rowq)
   float fitn[NSET][RPW]; // bandpass value of the row being staged (loaded with its quads)
   int32_t rowt[NSET][RPW]; // chunk index of the staged row's window start (uniform)
