@@ -227,10 +227,11 @@ mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_
  * Sums are FP32, channels accumulated in ascending order in blocks of 32
  * (a fixed order, so results do not depend on the tiling).  8-bit samples
  * without cleaning sum to integers below 2^24, which FP32 holds exactly:
- * such a chunk's outputs are the exact sums, whatever the tiling.  A
- * single-shot (or first streamed) 8-bit chunk without cleaning, whose rows
- * start 8-byte aligned with ld a multiple of 8, runs on an integer kernel
- * (16-bit partial sums) that gives these same bits faster.
+ * such a chunk's outputs are the exact sums, whatever the tiling.  For an
+ * 8-bit chunk without cleaning, longer than s_max, whose rows start 8-byte
+ * aligned with ld a multiple of 8, the outputs that read only the chunk's
+ * own samples run on an integer kernel (16-bit partial sums) that gives
+ * these same bits faster; info->integer_kernel reports it.
  *
  * beam == NULL: single shot over nsamps samples; nout = nsamps - s_max
  * outputs per DM (MB_EINVAL if nsamps <= s_max).

@@ -341,7 +341,11 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
   for (int k = nblk; k % kPF != 0; ++k) __syncthreads();
   fold();
   // ---- store: 8 outputs per lane and DM ----
+  // (A.out may start anywhere in a row, after outputs another launch writes:
+  // rows are a multiple of 4 floats apart, so whether a lane's 8 outputs
+  // are 16-byte aligned is the same for every lane and row)
   const int64_t j = (int64_t)t0 + 8 * lane;
+  const bool aligned = (reinterpret_cast<uintptr_t>(A.out) & 15) == 0;
 #pragma unroll
   for (int g = 0; g < kU8G; ++g) {
     const int d = d0 + aw * kU8G + g;
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(64 * kWaves) void dedisp_u8_kernel(DedispArgs A, co
     float f[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) f[i] = (float)tot[g][i];
-    if (j + 7 < A.nout) {
+    if (aligned && j + 7 < A.nout) {
       *reinterpret_cast<float4*>(orow + j) = make_float4(f[0], f[1], f[2], f[3]);
       *reinterpret_cast<float4*>(orow + j + 4) = make_float4(f[4], f[5], f[6], f[7]);
     } else {

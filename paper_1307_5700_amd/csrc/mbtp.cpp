@@ -604,11 +604,11 @@ mb_status prepare(const mb_plan* plan, mb_beam* beam, const void* d_in, int64_t 
   return MB_OK;
 }
 
-// Whether a prepared item runs on the exact integer kernel: 8-bit samples,
-// no cleaning, no ring samples staged, and rows the kernel can read as
-// aligned octets.  Its results equal the float kernels' bit for bit.
-bool uses_u8_int(const Prepared& P, bool ring) {
-  return P.plan->u8_int && !P.clean && !ring && P.a.phase == 0 &&
+// Whether a prepared item's outputs that read only its own chunk run on the
+// exact integer kernel: 8-bit samples, no cleaning, and rows the kernel can
+// read as aligned octets.  Its results equal the float kernels' bit for bit.
+bool uses_u8_int(const Prepared& P) {
+  return P.plan->u8_int && !P.clean && P.nsamps > P.plan->smax &&
          (reinterpret_cast<uintptr_t>(P.d_in) & 7) == 0 && P.ld % 8 == 0;
 }
 
@@ -637,12 +637,31 @@ mb_status dedisp_execute(const mb_plan* plan, mb_beam* beam, const void* d_in, i
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool ring = beam != nullptr && P.a.ring_valid > 0;
-  const bool integer = P.nout > 0 && uses_u8_int(P, ring);
+  const bool integer = P.nout > 0 && uses_u8_int(P);
   if (integer) {
+    // The last nsamps - s_max outputs read only this chunk's samples: the
+    // integer kernel sums them as a single shot over the chunk.  With ring
+    // samples staged, the float ring kernel forms the outputs before them
+    // (the first min(seen, s_max), which read ring samples too).
+    const int64_t n2 = P.nsamps - plan->smax, n1 = P.nout - n2;
+    if (ring && n1 > 0) {
+      DedispArgs a = P.a;
+      a.nout = n1;
+      a.n_ttiles = (int32_t)((a.phase + n1 + plan->tiling.BT() - 1) / plan->tiling.BT());
+      HIP_TRY(launch_dedisp(plan->desc.in_dtype, false, true, plan->tiling, a, plan->d_relb, P.fit32, plan->lds, s));
+    }
     DedispArgs a = P.a;
+    a.ring = nullptr;
+    a.R = 0;
+    a.ring_valid = 0;
+    a.ring_p0 = 0;
+    a.phase = 0;
+    a.seen_dev = nullptr;
+    a.nout = n2;
+    a.out = P.d_out + n1;
     a.rs = plan->rs8;
     a.n_dblocks = (plan->desc.ndms + kU8BD - 1) / kU8BD;
-    a.n_ttiles = (int32_t)((P.nout + kU8BT - 1) / kU8BT);
+    a.n_ttiles = (int32_t)((n2 + kU8BT - 1) / kU8BT);
     HIP_TRY(launch_dedisp_u8(a, plan->d_relb8, plan->lds8, s));
   } else if (P.nout > 0) {
     HIP_TRY(launch_dedisp(plan->desc.in_dtype, P.clean, ring, plan->tiling, P.a, plan->d_relb, P.fit32,

@@ -73,10 +73,12 @@ def test_integer_kernel_with_saturated_samples():
     assert np.all(D == np.float32(1024 * 255))
 
 
-def test_integer_kernel_first_chunk_of_a_stream_equals_single_shot():
-    """A stream's first chunk stages no ring samples and runs on the integer
-    kernel; later chunks run on the float ring kernel.  The stream's outputs
-    equal a single shot over the concatenated chunks, bit for bit."""
+def test_streamed_chunks_equal_single_shot():
+    """Streamed 8-bit chunks without cleaning: the outputs that read only
+    the new chunk run on the integer kernel (all of the first chunk's), the
+    ones that reach back into the ring on the float ring kernel.  The
+    stream's outputs equal a single shot over the concatenated chunks, bit
+    for bit."""
     A = api()
     T = 4096 * 3
     b, s = _beam(512, 96, T)
@@ -86,11 +88,34 @@ def test_integer_kernel_first_chunk_of_a_stream_equals_single_shot():
     outs = []
     for k in range(3):
         out, _, nout, s0 = plan.execute(to_dev(x[:, k * 4096:(k + 1) * 4096], 4096), beam=beam)
-        assert plan.last_integer_kernel == (k == 0)
+        assert plan.last_integer_kernel
         outs.append(out[:, :nout].cpu().numpy())
     single, nout = _run(plan, x, T, integer=True)
     assert np.array_equal(np.concatenate(outs, axis=1), single)
 
+
+def test_stream_after_a_cleaned_chunk_equals_the_float_kernels():
+    """A cleaned chunk leaves cleaned (fractional) samples in the ring; the
+    raw chunks after it still equal a stream that runs only float kernels
+    (rows of stride 4 mod 8), bit for bit, including the outputs that read
+    those ring samples."""
+    A = api()
+    L, n = 4096, 4
+    b, s = _beam(512, 96, L * n)
+    x = synth.render(b, s)
+    res = []
+    for ld, integer in ((L, True), (L + 4, False)):
+        plan = A.Plan.from_beam(b)
+        beam = A.Beam(plan)
+        outs = []
+        for k in range(n):
+            xd = to_dev(x[:, k * L:(k + 1) * L], ld)
+            st = plan.rfi_threshold(xd) if k == 1 else None
+            out, _, nout, _ = plan.execute(xd, rfi_state=st, beam=beam)
+            assert plan.last_integer_kernel == (integer and k != 1)
+            outs.append(out[:, :nout].cpu().numpy())
+        res.append(np.concatenate(outs, axis=1))
+    assert np.array_equal(res[0], res[1])
 
 
 def test_cleaning_and_other_storage_types_take_the_float_kernels():
