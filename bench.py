@@ -103,6 +103,9 @@ TRAFFIC = {
                 "one cluster_union_kernel launch, cluster workload (53858 detections, 640 DMs)"),
     "power": ("power_kernel", "power_traffic.txt", ("power.hip", "internal.h"),
               "one power_kernel launch, power workload (1024 ch x 65536 int16 complex voltage samples)"),
+    "batch": ("dedisp_batch_kernel", "dedisp_batch_traffic.txt",
+              ("dedisp.hip", "tile_map.h", "rfi.hip", "detect.hip", "internal.h"),
+              "one dedisp_batch_kernel launch, batch workload (8 uneven u8 beams, RFI on, steady-state streams)"),
 }
 
 
@@ -226,6 +229,9 @@ STATS = {
                 "kernel trace of the cluster workload (53858 detections over 640 DMs x 59434 samples)"),
     "power": ("power_1024ch_65536samp_kernel_stats.txt",
               "kernel trace of the power workload (1024 ch x 65536 int16 complex voltage samples)"),
+    "batch": ("batch_8beams_u8_kernel_stats.txt",
+              "kernel trace of the batch workload (8 uneven u8 beams, 512-2048 ch, 320-1280 DMs, "
+              "16384-131072 samples, RFI on)"),
 }
 
 
@@ -239,6 +245,8 @@ def _event_kernel_ms(workload: str, res: dict):
         return res["encode_kernel_ms"]
     if workload in ("power", "cluster", "paper_u8"):
         return res["kernel_ms"]
+    if workload == "batch":
+        return res["roofline"]["kernel_ms"]
     return None
 
 
@@ -705,6 +713,7 @@ def bench_batch(args):
     g = A.BatchGraph(plans, xs, bms, rfi=True, nsigma=6.0)
     dt = _timed(g.replay, args.steps, args.warmup)
     samples = g.dm_trial_samples
+    _progress(f"batch: captured step {dt * 1e3:.3f} ms")
     # error of the last replay against the FP64 oracle on sampled rows: every
     # chunk of these streams is the same data, so the replayed chunk's outputs
     # are the oracle's dedispersion of the cleaned chunk preceded by the last
@@ -722,7 +731,36 @@ def bench_batch(args):
         D = out[torch.from_numpy(rows).cuda(), :L_].cpu().numpy().astype(np.float64)
         scale = np.maximum(np.abs(ref), ref.std(axis=1, keepdims=True))
         errs.append(float(np.max(np.abs(D - ref) / scale)))
+        _progress(f"batch: beam {len(errs)} of {len(beams)} against the oracle, error {errs[-1]:.2e}")
     del g
+
+    # The persistent launch alone: the same beams in steady state, eager,
+    # dedispersion only (each beam's RFI state taken once), timed by HIP
+    # events on the current stream.  Its adds per second against the FP32
+    # add peak; these are the last dispatches of the kernel in the run.
+    states = [p.rfi_threshold(x) for p, x in zip(plans, xs)]
+    jobs = [dict(plan=p, x=x, rfi_state=st, beam=bm, out=p.alloc_output(x.shape[1]), norm=False)
+            for p, x, st, bm in zip(plans, xs, states, bms)]
+    work = A.alloc_batch_work(len(jobs), plans[0].device)
+    first = A.execute_batch(jobs, work=work)
+    adds = float(sum(p.nchans * p.ndms * r[2] for p, r in zip(plans, first)))
+    for _ in range(args.warmup):
+        A.execute_batch(jobs, work=work)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        A.execute_batch(jobs, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / args.steps
+    achieved = adds / (k_ms * 1e-3) / 1e12
+    _progress(f"batch: persistent launch {k_ms:.3f} ms, {achieved:.2f}e12 adds/s")
+    del jobs, states, work
+    if args.calib_copy:
+        _calib_copy()
+    traffic = _traffic("batch")
 
     # the plain path: FP32 storage, default tiling, one beam after another
     plain = []
@@ -753,6 +791,14 @@ def bench_batch(args):
         "plain_f32_single_beam": {"value": samples / dt_plain, "ms_per_step": dt_plain * 1e3,
                                   "path": "FP32 storage, default tiling, eager, one beam at a time"},
         "speedup_vs_plain_f32": dt_plain / dt,
+        "roofline": {"bound": "alu", "kernel": "dedisp_batch_kernel", "achieved": achieved,
+                     "peak": PEAK_FP32_ADD_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_ADD_TFLOPS,
+                     "traffic": traffic, "kernel_ms": k_ms, "adds_per_launch": adds,
+                     "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+                     "frac_of_unpacked_add_peak": achieved / PEAK_FP32_ADD_UNPACKED_TFLOPS,
+                     "work": "C FP32 adds per DM-trial sample of every beam, one launch over the 8 beams",
+                     "timed": "HIP events around each batched call: the persistent launch, its counter reset "
+                              "and the rings' updates"},
         "err_vs_fp64_oracle": max(errs), "err_per_beam": errs,
         "error_metric": "max over 3-4 sampled DM rows per beam of |D - D*| / max(|D*|, std_t D*), "
                         "the replayed streaming chunk against the FP64 oracle"})
