@@ -242,6 +242,12 @@ mb_status rfi_report(const mb_plan* plan, const void* d_state, mb_rfi_report* h_
  * samples have been seen), starting at absolute sample
  * max(0, seen - s_max), "seen" counting the samples before this chunk.
  *
+ * d_in holds C rows ld samples apart (ld >= nsamps, a multiple of 4, the
+ * pointer 16-byte aligned).  The kernels load aligned groups of 4 samples
+ * (8 on the integer kernel) whole, so every row must be readable up to
+ * sample min(ld, nsamps rounded up to a multiple of 8); samples past nsamps
+ * enter no sum.
+ *
  * d_norm (nullable, [ndms]) receives each DM's detrend line and scale over
  * the outputs of this call (Sec. 2.2.3).  info (nullable, host) receives
  * nout and sample0.  d_out must be 16-byte aligned with ld_out >= nout a

@@ -114,7 +114,15 @@ class Plan:
             raise ValueError("input must be a [nchans, T] tensor with unit time stride on the plan's GPU")
         if x.dtype != TORCH_DTYPES[self.dtype]:
             raise ValueError(f"input dtype {x.dtype} does not match the plan ({self.dtype})")
-        return x.shape[1], x.stride(0)
+        T, ld = x.shape[1], x.stride(0)
+        # rows are loaded in aligned groups of 4 samples (8 on the integer
+        # kernel): the last row must be readable up to min(ld, T rounded up to
+        # 8).  (A misaligned start is left to the library to refuse.)
+        need = x.storage_offset() + (x.shape[0] - 1) * ld + min(ld, (T + 7) // 8 * 8)
+        if x.data_ptr() % 16 == 0 and x.untyped_storage().nbytes() < need * x.element_size():
+            raise ValueError(f"input storage ends before sample {min(ld, (T + 7) // 8 * 8)} of its last row "
+                             "(rows are read in aligned groups of up to 8 samples)")
+        return T, ld
 
     def alloc_output(self, nout: int) -> torch.Tensor:
         ld = (int(nout) + 3) // 4 * 4

@@ -190,3 +190,25 @@ def test_paper_beam_in_8_bits_at_full_size():
     assert np.array_equal(D8[rows].astype(np.float64), ref)
     Df, _ = _run(plan, x, x.shape[1] + 4, integer=False)
     assert np.array_equal(Df, D8)
+
+
+def test_input_storage_must_reach_the_last_rows_group():
+    """Rows are read in aligned groups of up to 8 samples: an input whose
+    storage ends inside the last row's last group is refused before any
+    launch, and one whose storage reaches that group's end runs (here on the
+    integer kernel, exact)."""
+    A = api()
+    C, nd, T, ld = 256, 64, 8196, 8200
+    b, s = _beam(C, nd, T)
+    x = synth.render(b, s)
+    plan = A.Plan.from_beam(b)
+    short = torch.zeros((C - 1) * ld + T, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError, match="storage"):
+        plan.execute(short.as_strided((C, T), (ld, 1)))
+    full = torch.zeros((C - 1) * ld + ld, dtype=torch.uint8, device="cuda")
+    xf = full.as_strided((C, T), (ld, 1))
+    xf.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+    out, _, nout, _ = plan.execute(xf)
+    torch.cuda.synchronize()
+    assert plan.last_integer_kernel
+    assert np.array_equal(out[:, :nout].cpu().numpy(), oracle.dedisperse(x, s).astype(np.float32))
