@@ -73,6 +73,23 @@ def test_integer_kernel_with_saturated_samples():
     assert np.all(D == np.float32(1024 * 255))
 
 
+def test_integer_kernel_with_8192_channels():
+    """8192 channels: 32 widenings of the 16-bit partials into the 32-bit
+    totals.  All-255 input gives C * 255 = 2088960 everywhere (exact in
+    FP32), and a rendered beam equals the oracle's sums exactly."""
+    A = api()
+    C, nd, T = 8192, 48, 4096
+    b, s = _beam(C, nd, T)
+    plan = A.Plan.from_beam(b)
+    assert plan.tiling["u8_integer"]
+    D, nout = _run(plan, np.full((C, T), 255, dtype=np.uint8), T, integer=True)
+    assert nout == T - int(s.max())
+    assert np.all(D == np.float32(C * 255))
+    x = synth.render(b, s)
+    D, _ = _run(plan, x, T, integer=True)
+    assert np.array_equal(D, oracle.dedisperse(x, s).astype(np.float32))
+
+
 def test_streamed_chunks_equal_single_shot():
     """Streamed 8-bit chunks without cleaning: the outputs that read only
     the new chunk run on the integer kernel (all of the first chunk's), the
